@@ -1,0 +1,177 @@
+"""Throughput of the fused 2SHOC-RK4 stage kernels on the 2D Gross-Pitaevskii workload.
+
+Workload: a = 0.5, s = -1, V = 0.5 (0.05)^2 r^2 on [-40, 40]^2, 2048 intervals per axis
+(2049^2 nodes, 2047^2 interior points), Dirichlet 0, vortex in a Thomas-Fermi cloud
+plus 1e-3 seeded complex noise; dt = 0.5 x the stability bound (4.0415e-4).  One
+"step" is one classic RK4 step (four fused stage kernels) over the whole grid.
+Inputs are resident in HBM before the timed region; K steps are timed with HIP
+events on the solver's stream, bracketed by device synchronisation.
+
+Prints one JSON line.  value = interior points x RK4 steps / s / 1e9 (FP64 path).
+roofline: algorithmic bytes of the stage kernel per launch (76 B per interior point
+for complex128: 304 B per point-step over 4 launches) / its mean launch time.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per interior point and RK4 step (4 fused stages, V stored):
+#   complex128 17*16 + 4*8 = 304; complex64 17*8 + 4*4 = 152; mixed (complex128 master) 192
+BYTES_PER_POINT_STEP = {"f64": 304, "f32": 152, "mixed": 192}
+METRIC = "2SHOC-RK4 Gpt·steps/s + % HBM peak; coarse+learned vs plain fine at equal L2 err"
+KERNEL_SRC = os.path.join(ROOT, "paper_1109_1027_amd", "csrc", "stage2d.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage2d_gp2d_2048.json")
+
+
+def kernel_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(prec, launches_ratio=1.0):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they match this kernel source."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != kernel_sha() or prec not in t.get("per_launch_bytes", {}):
+        return None
+    return t["per_launch_bytes"][prec]
+
+
+def time_solver(P, spec, prec, steps, warmup):
+    import torch
+    s = P.Solver.from_spec(spec, prec=prec)
+    s.set_field(spec.psi0)
+    dt = 0.5 * s.max_dt()
+    s.step(warmup, dt)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step(steps, dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    mass = s.mass()
+    launches = s.launches_per_step() * steps
+    s.close()
+    return ms, wall, launches, dt, mass
+
+
+def copy_ceiling_gbs():
+    """Achieved GB/s of a plain device copy of 1 GiB (read + write), for context."""
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 10 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def cpu_baseline(spec, budget_s=12.0):
+    """The FP64 oracle on the same grid, a bounded number of RK4 steps on the host cores."""
+    import oracle
+    P = oracle.Problem.from_spec(spec)
+    dt = 0.5 * P.max_dt(spec.psi0)
+    psi = spec.psi0
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        psi = P.rk4(psi, 1, dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 50:
+            break
+    return {"value": spec.interior_points * steps / el / 1e9, "unit": "Gpt·steps/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{steps} RK4 steps of the FP64 oracle on the full 2049^2 grid ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=2048, help="intervals per axis")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precs", default="f64,f32,mixed")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(instances of the solver shard by domain slabs, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import nlse_inputs as I
+    import paper_1109_1027_amd as P
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    P.load()
+    spec = I.config_gp2d(n=args.n)
+    npts = spec.interior_points
+    precs = args.precs.split(",")
+    res = {}
+    for prec in precs:
+        ms, wall, launches, dt, mass = time_solver(P, spec, prec, args.steps, args.warmup)
+        gpts = npts * args.steps / (ms * 1e-3) / 1e9
+        per_launch_bytes = BYTES_PER_POINT_STEP[prec] * npts / 4
+        avg_launch_s = ms * 1e-3 / launches
+        achieved = per_launch_bytes / avg_launch_s / 1e9
+        tr = measured_traffic(prec)
+        res[prec] = {
+            "value": gpts, "ms_per_step": ms / args.steps, "wall_s": wall, "dt": dt, "mass_end": mass,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
+                         "kernel": "nlse::stage2d_kernel", "algorithmic_bytes_per_launch": per_launch_bytes,
+                         "avg_launch_us": avg_launch_s * 1e6},
+        }
+        print(f"[bench] {prec}: {gpts:.2f} Gpt*steps/s, {ms / args.steps:.4f} ms/step, "
+              f"{achieved:.0f} GB/s algorithmic ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)",
+              file=sys.stderr, flush=True)
+    main_prec = precs[0]
+    out = {
+        "metric": METRIC, "value": res[main_prec]["value"], "unit": "Gpt·steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res[main_prec]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "mixed": "f32+f64"}[main_prec], "data": "synthetic",
+        "config": {"workload": "2D Gross-Pitaevskii 2SHOC-RK4, 2049^2 nodes (2047^2 interior), "
+                               "a=0.5 s=-1 omega=0.05 on [-40,40]^2, Dirichlet 0, vortex+1e-3 noise, "
+                               f"dt=0.5*k_max={res[main_prec]['dt']:.6g}",
+                   "grid_nodes": [args.n + 1, args.n + 1], "interior_points": npts,
+                   "precision": main_prec, "parallelism": "single GPU"},
+        "roofline": res[main_prec]["roofline"],
+        "variants": {p: {k: v for k, v in r.items() if k in ("value", "ms_per_step", "roofline")}
+                     for p, r in res.items() if p != main_prec},
+    }
+    try:
+        out["copy_ceiling_gbs"] = copy_ceiling_gbs()
+    except Exception as e:  # context only
+        out["copy_ceiling_gbs"] = None
+        print(f"[bench] copy ceiling failed: {e}", file=sys.stderr)
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,139 @@
+/*
+ * nlse.h -- C ABI of the MI355X (gfx950) 2SHOC-RK4 solver for the nonlinear
+ * Schroedinger / Gross-Pitaevskii equation
+ *
+ *     i Psi_t + a Lap(Psi) - V(r) Psi + s |Psi|^2 Psi = 0,   a > 0      (Sec. 1, Eq. NLSE)
+ *
+ * on a uniform 1D, 2D or 3D grid with the same step h on every axis (Sec. 2).
+ * Each RK4 step (Sec. 3.1, Eq. RK4) evaluates F(Psi) = i[a Lap + (s|Psi|^2 - V)Psi]
+ * four times; Lap is the two-step high-order compact (2SHOC) Laplacian
+ * (Sec. 2.1-2.3): step 1 a second difference D, step 2 a compact combination of
+ * D that is fourth-order accurate.  Boundary closures follow Sec. 3.2 (Dirichlet
+ * Eqs. dbc_lap / dbc_ut; modulus-squared Dirichlet, 1D only, Eqs. msdbc_lap /
+ * msdbc_ut).  Every step runs in hand-written HIP kernels on the GPU.
+ *
+ * Conventions shared by every entry point
+ *   - Grid: n[a] intervals per axis, n[a] + 1 nodes including both boundary
+ *     nodes; node i on axis a sits at x_min + i h.
+ *   - Fields: dense, C order [z][y][x] (x fastest), complex values interleaved
+ *     (re, im).  Element type: complex128 (two doubles) for NLSE_F64 and
+ *     NLSE_F32_MIXED, complex64 (two floats) for NLSE_F32.
+ *   - Pointers flagged on_device are device pointers (e.g. from torch) and the
+ *     copy is ordered on the context's stream; otherwise they are host pointers
+ *     and the call returns when the copy is complete.  The library never keeps
+ *     a caller pointer: inputs are copied in, outputs copied out.
+ *   - Ownership: a context owns all its device memory; nlse_destroy frees it.
+ *   - Streams: all GPU work of a context is enqueued on params.stream (a
+ *     hipStream_t; NULL = the default stream).  nlse_step returns without
+ *     waiting; nlse_mass / nlse_energy / nlse_max_dt and host-side
+ *     get_field wait for the stream.
+ *   - Errors: every call returns an nlse_status; on failure nlse_last_error()
+ *     returns a thread-local message.  No exception crosses the ABI.  A context
+ *     must not be used from two threads at once.
+ */
+#ifndef NLSE_H
+#define NLSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nlse_ctx nlse_ctx;
+
+typedef enum {
+    NLSE_OK = 0,
+    NLSE_E_INVAL = -1,         /* NULL pointer, bad size, a <= 0, h <= 0, ... */
+    NLSE_E_DT_UNSTABLE = -2,   /* dt above the stability bound (see nlse_step) */
+    NLSE_E_NONFINITE = -3,     /* a reduction met NaN or Inf in the field */
+    NLSE_E_NOMEM = -4,         /* device allocation failed */
+    NLSE_E_HIP = -5,           /* a HIP runtime call failed */
+    NLSE_E_UNSUPPORTED = -6    /* valid but not implemented (e.g. MSD in 2D/3D) */
+} nlse_status;
+
+typedef enum {
+    NLSE_F64 = 0,        /* complex128 storage and arithmetic */
+    NLSE_F32 = 1,        /* complex64 storage and arithmetic */
+    NLSE_F32_MIXED = 2   /* complex64 stage fields, stencil and RK4 stage sums;
+                            complex128 master Psi^n: the final RK4 accumulation
+                            Psi^{n+1} = Psi^n + (k/6)(K_tot + K_4) adds an FP32
+                            increment in FP64; mass / energy in FP64 */
+} nlse_precision;
+
+typedef enum {
+    NLSE_BC_DIRICHLET = 0, /* boundary nodes keep their initial values (Eq. dbc_ut);
+                              step-1 boundary value from Eq. dbc_lap */
+    NLSE_BC_MSD = 1        /* |Psi_b|^2 constant (Eqs. msdbc_ut, msdbc_lap); 1D only */
+} nlse_bc;
+
+typedef struct {
+    int32_t ndim;          /* 1, 2 or 3 */
+    int64_t n[3];          /* intervals per axis (n[a] >= 2 for a < ndim) */
+    double h;              /* grid step, > 0, the same on every axis */
+    double a;              /* dispersion coefficient, > 0 */
+    double s;              /* nonlinearity coefficient */
+    const double *V;       /* host array of (n+1)^ndim reals in field order, or NULL for V = 0;
+                              copied at nlse_create */
+    int32_t bc;            /* nlse_bc */
+    int32_t prec;          /* nlse_precision */
+    int32_t allow_unstable;/* nonzero: nlse_step skips the dt check */
+    void *stream;          /* hipStream_t or NULL */
+} nlse_params;
+
+/* Create a context: validates params, allocates the resident device arrays
+ * (Psi^n, two ping-pong stage fields, K_tot, V) and copies V.  The field is
+ * zero until nlse_set_field.  Returns NLSE_E_INVAL for invalid params and
+ * NLSE_E_UNSUPPORTED for MSD with ndim > 1. */
+int nlse_create(nlse_ctx **out, const nlse_params *p);
+
+/* Copy a full field (all (n+1)^ndim nodes, boundary included) into the context.
+ * Under Dirichlet the boundary values given here are held fixed from then on.
+ * Also evaluates the stability bound of nlse_max_dt on this field (waits for
+ * the stream) and stores it for nlse_step's check. */
+int nlse_set_field(nlse_ctx *c, const void *psi, int on_device);
+
+/* Advance nsteps classic RK4 steps of size dt (Sec. 3.1), enqueued on the
+ * context stream (asynchronous).  Returns NLSE_E_DT_UNSTABLE, doing nothing,
+ * when dt exceeds the bound stored by the last nlse_set_field and the context
+ * was created with allow_unstable = 0; NLSE_E_INVAL for dt <= 0 or nsteps < 0. */
+int nlse_step(nlse_ctx *c, int64_t nsteps, double dt);
+
+/* Copy the current field out (same layout and element type as nlse_set_field). */
+int nlse_get_field(nlse_ctx *c, void *out, int on_device);
+
+/* Mass h^d sum_{all nodes} |Psi|^2, accumulated in FP64 in a fixed order
+ * (bitwise reproducible run to run).  NLSE_E_NONFINITE if the sum is not finite. */
+int nlse_mass(nlse_ctx *c, double *out);
+
+/* Energy h^d sum_{interior} [ -a Re(conj(Psi) Lap Psi) + V|Psi|^2 - (s/2)|Psi|^4 ]
+ * with the 2SHOC Laplacian, accumulated in FP64 (the Hamiltonian of Eq. NLSE). */
+int nlse_energy(nlse_ctx *c, double *out);
+
+/* Linearised stability bound on the current field (Sec. 3.3, Eq. kdfull):
+ *   k_max = sqrt(8) h^2 / (a max(|B|_inf, G_max - L_min, L_max - G_min)),
+ *   L_i = (h^2/a)(s|Psi_i|^2 - V_i) over interior nodes, (G_max, G_min) =
+ *   (64, -4)/12, (128, -8)/12, (192, -12)/12 in 1D / 2D / 3D (Table
+ *   t:sumresults), B_b = 0 for Dirichlet and (h^2/(i a)) F_{b-1}/Psi_{b-1} for
+ *   MSD (Table t:bc2). */
+int nlse_max_dt(nlse_ctx *c, double *out);
+
+/* Wait until all work enqueued by the context has finished. */
+int nlse_sync(nlse_ctx *c);
+
+/* Free everything the context owns.  NULL is ignored. */
+void nlse_destroy(nlse_ctx *c);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *nlse_last_error(void);
+
+/* Number of kernel launches one RK4 step enqueues for this context (4 for the
+ * tiled 2D/3D stage kernels; 1D contexts advance all steps in one launch and
+ * report 0).  For throughput accounting. */
+int nlse_launches_per_step(const nlse_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NLSE_H */

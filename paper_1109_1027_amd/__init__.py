@@ -1,0 +1,8 @@
+"""MI355X (gfx950) 2SHOC-RK4 solver for the nonlinear Schroedinger equation.
+
+The numerical work runs in hand-written HIP kernels behind the C ABI of
+``include/nlse.h``; ``nlse.Solver`` is a thin ctypes binding of it.
+"""
+from .nlse import NLSEError, Solver, load  # noqa: F401
+
+__all__ = ["Solver", "NLSEError", "load"]

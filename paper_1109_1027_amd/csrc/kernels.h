@@ -1,0 +1,70 @@
+// Host-side launchers of the device kernels (one translation unit per family).
+#pragma once
+
+#include "common.h"
+
+namespace nlse {
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_MIXED = 2 };
+
+// Arguments of one fused RK4-stage launch (2D and 3D share the struct).
+//   stage 1: in = Psi^n            K = F          out = Psi^n + (k/2) F
+//   stage 2: in = Psi_tmp          K += 2F        out = Psi^n + (k/2) F
+//   stage 3: in = Psi_tmp          K += 2F        out = Psi^n + k F
+//   stage 4: in = Psi_tmp          Psi^n = Psi^n + (k/6)(K + F)
+// Only interior nodes are written; boundary nodes of every stage field hold the
+// fixed Dirichlet values.
+struct StageArgs {
+    const void *in;     // stencil input field
+    void *out;          // stage output (stages 1-3)
+    void *psin;         // master Psi^n
+    void *K;            // K_tot
+    const void *V;      // potential (real) or nullptr
+    const void *DB[3];  // boundary-face normal second differences, per axis [2][face nodes]
+    Layout L;
+    Coeffs c;
+    int stage;
+};
+
+// 2D fused stage kernel: per-axis 2SHOC, one 64-column x RW-row tile per wave.
+hipError_t launch_stage2d(Prec prec, const StageArgs &a, hipStream_t st);
+// 3D fused stage kernel (2.5D: x-y tile in LDS, march along z).
+hipError_t launch_stage3d(Prec prec, const StageArgs &a, hipStream_t st);
+
+// 1D persistent solver: one workgroup holds the whole field on chip and runs
+// nsteps RK4 steps in one launch.
+struct Solve1DArgs {
+    void *psin;          // master Psi^n (in/out)
+    const void *V;       // real potential or nullptr
+    Layout L;
+    Coeffs c;            // ck unused; k, k/2, k/6 below
+    double k, k2, k6;
+    int64_t nsteps;
+    int msd;             // 1: MSD boundary, 0: Dirichlet
+};
+hipError_t launch_solve1d(Prec prec, const Solve1DArgs &a, hipStream_t st);
+int64_t solve1d_max_nodes(Prec prec);
+
+// Boundary-face normal second differences D^a_b = Lap_b - sum_{tangential} delta^2 Psi_b
+// for the per-axis 2SHOC (Dirichlet, 2D/3D), from the master field.
+hipError_t launch_boundary_d(Prec prec, const void *psin, const void *V, const Layout &L,
+                             const Coeffs &c, void *DB[3], hipStream_t st);
+
+// Copy the master field into a stage field, converting to the stage type.
+hipError_t launch_master_to_stage(Prec prec, const void *psin, void *dst, const Layout &L,
+                                  hipStream_t st);
+
+// Deterministic FP64 reductions.  `partials` must hold reduce_partials() doubles
+// (times 2 for minmax); the result is written to dev_out (device) and is
+// bitwise reproducible for a given layout.
+int reduce_partials();
+hipError_t launch_mass(Prec prec, const void *psin, const Layout &L, double *partials,
+                       double *dev_out, hipStream_t st);
+hipError_t launch_energy(Prec prec, const void *psin, const void *V, const void *const DB[3],
+                         const Layout &L, const Coeffs &c, double *partials, double *dev_out,
+                         hipStream_t st);
+// dev_out[0] = min over interior of (s|Psi|^2 - V), dev_out[1] = max.
+hipError_t launch_minmax_nonlin(Prec prec, const void *psin, const void *V, const Layout &L,
+                                double s, double *partials, double *dev_out, hipStream_t st);
+
+}  // namespace nlse

@@ -1,0 +1,422 @@
+// Host runtime and C ABI of the 2SHOC-RK4 library (declarations in include/nlse.h).
+//
+// A context owns, in the padded device layout of common.h:
+//   psi   master Psi^n            (complex128 for F64 / MIXED, complex64 for F32)
+//   A, B  ping-pong stage fields  (complex in the stage precision)
+//   K     K_tot                   (stage precision)
+//   V     potential               (real, stage precision; absent when V = 0)
+//   DB    boundary-face closure values of the per-axis 2SHOC (2D / 3D)
+// One RK4 step enqueues four fused stage kernels (2D / 3D):
+//   S1 psi -> A, S2 A -> B, S3 B -> A, S4 A -> psi
+// The ping-pong keeps every stage's stencil input read-only while the next stage
+// field is written.  1D contexts run all steps in one persistent launch.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "../../include/nlse.h"
+
+using namespace nlse;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hipfail(hipError_t e, const char *what)
+{
+    return fail(NLSE_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPTRY(call)                                         \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hipfail(e_, #call);     \
+    } while (0)
+
+}  // namespace
+
+struct nlse_ctx {
+    nlse_params p;
+    Layout L;
+    Prec prec;
+    size_t esR, esM, rR;        // bytes: stage complex, master complex, stage real
+    void *psi = nullptr, *A = nullptr, *B = nullptr, *K = nullptr, *V = nullptr;
+    void *DB[3] = {nullptr, nullptr, nullptr};
+    double *red = nullptr;      // reduction partials (2 * reduce_partials()) + 2 result slots
+    hipStream_t stream = nullptr;
+    double kmax = 0.0;
+    bool have_field = false;
+    std::vector<double> Vhost; // for host-side MSD closure (1D)
+};
+
+static Coeffs base_coeffs(const nlse_params &p)
+{
+    Coeffs c;
+    c.a = p.a;
+    c.s = p.s;
+    c.ih2 = 1.0 / (p.h * p.h);
+    c.c76 = 7.0 / 6.0;
+    c.c112 = 1.0 / 12.0;
+    c.ia = 1.0 / p.a;
+    c.ck = 0.0;
+    return c;
+}
+
+static int64_t face_nodes(const Layout &L, int axis)
+{
+    const int64_t nn[3] = {L.nx, L.ny, L.nz};
+    int64_t f = 1;
+    for (int b = 0; b < L.dim; ++b)
+        if (b != axis) f *= nn[b] + 1;
+    return f;
+}
+
+static void free_ctx(nlse_ctx *c)
+{
+    if (!c) return;
+    void *bufs[] = {c->psi, c->A, c->B, c->K, c->V, c->DB[0], c->DB[1], c->DB[2], c->red};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    delete c;
+}
+
+extern "C" {
+
+const char *nlse_last_error(void) { return g_err.c_str(); }
+
+int nlse_create(nlse_ctx **out, const nlse_params *p)
+{
+    if (!out || !p) return fail(NLSE_E_INVAL, "nlse_create: NULL argument");
+    *out = nullptr;
+    if (p->ndim < 1 || p->ndim > 3) return fail(NLSE_E_INVAL, "ndim must be 1, 2 or 3");
+    for (int a = 0; a < p->ndim; ++a)
+        if (p->n[a] < 2) return fail(NLSE_E_INVAL, "n[a] must be >= 2 intervals");
+    if (!(p->h > 0.0) || !std::isfinite(p->h)) return fail(NLSE_E_INVAL, "h must be > 0");
+    if (!(p->a > 0.0) || !std::isfinite(p->a)) return fail(NLSE_E_INVAL, "a must be > 0");
+    if (!std::isfinite(p->s)) return fail(NLSE_E_INVAL, "s must be finite");
+    if (p->bc != NLSE_BC_DIRICHLET && p->bc != NLSE_BC_MSD) return fail(NLSE_E_INVAL, "unknown bc");
+    if (p->prec != NLSE_F64 && p->prec != NLSE_F32 && p->prec != NLSE_F32_MIXED)
+        return fail(NLSE_E_INVAL, "unknown precision");
+    if (p->bc == NLSE_BC_MSD && p->ndim != 1)
+        return fail(NLSE_E_UNSUPPORTED, "the MSD boundary is implemented in 1D only");
+    if (p->bc == NLSE_BC_MSD && p->n[0] < 4) return fail(NLSE_E_INVAL, "MSD needs n >= 4 intervals");
+
+    nlse_ctx *c = new nlse_ctx();
+    c->p = *p;
+    c->p.V = nullptr;
+    c->L = make_layout(p->ndim, p->n);
+    c->prec = (Prec)p->prec;
+    c->esR = c->prec == P_F64 ? 16 : 8;
+    c->esM = c->prec == P_F32 ? 8 : 16;
+    c->rR = c->esR / 2;
+    c->stream = (hipStream_t)p->stream;
+    if (p->ndim == 1 && c->L.nx + 1 > solve1d_max_nodes(c->prec)) {
+        free_ctx(c);
+        return fail(NLSE_E_UNSUPPORTED, "1D field larger than the on-chip solver holds");
+    }
+
+    const size_t T = (size_t)c->L.total;
+    auto alloc = [&](void **ptr, size_t bytes) -> int {
+        hipError_t e = hipMalloc(ptr, bytes);
+        if (e != hipSuccess) return fail(NLSE_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        e = hipMemset(*ptr, 0, bytes);
+        if (e != hipSuccess) return hipfail(e, "hipMemset");
+        return NLSE_OK;
+    };
+    int rc = alloc(&c->psi, T * c->esM);
+    if (!rc && p->ndim > 1) rc = alloc(&c->A, T * c->esR);
+    if (!rc && p->ndim > 1) rc = alloc(&c->B, T * c->esR);
+    if (!rc && p->ndim > 1) rc = alloc(&c->K, T * c->esR);
+    for (int a = 0; a < p->ndim && !rc; ++a) rc = alloc(&c->DB[a], 2 * (size_t)face_nodes(c->L, a) * c->esR);
+    if (!rc) rc = alloc((void **)&c->red, (2 * (size_t)reduce_partials() + 4) * sizeof(double));
+    if (!rc && p->V) {
+        rc = alloc(&c->V, T * c->rR);
+        if (!rc) {
+            // convert to the stage precision and scatter rows into the padded layout
+            const int64_t rows = c->L.py * (c->L.nz + 1), w = c->L.nx + 1;
+            std::vector<unsigned char> host((size_t)rows * w * c->rR);
+            for (int64_t i = 0; i < rows * w; ++i) {
+                if (c->rR == 8) ((double *)host.data())[i] = p->V[i];
+                else ((float *)host.data())[i] = (float)p->V[i];
+            }
+            hipError_t e = hipMemcpy2D((char *)c->V + c->L.ox * c->rR, c->L.px * c->rR, host.data(),
+                                       w * c->rR, w * c->rR, rows, hipMemcpyHostToDevice);
+            if (e != hipSuccess) rc = hipfail(e, "hipMemcpy2D(V)");
+            if (p->ndim == 1) c->Vhost.assign(p->V, p->V + w);
+        }
+    }
+    if (rc) {
+        free_ctx(c);
+        return rc;
+    }
+    *out = c;
+    return NLSE_OK;
+}
+
+void nlse_destroy(nlse_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_ctx(c);
+}
+
+int nlse_launches_per_step(const nlse_ctx *c)
+{
+    if (!c) return fail(NLSE_E_INVAL, "NULL context");
+    return c->p.ndim == 1 ? 0 : 4;
+}
+
+int nlse_sync(nlse_ctx *c)
+{
+    if (!c) return fail(NLSE_E_INVAL, "NULL context");
+    HIPTRY(hipStreamSynchronize(c->stream));
+    return NLSE_OK;
+}
+
+static int copy_field(nlse_ctx *c, void *dev_field, void *user, int on_device, bool to_dev)
+{
+    const Layout &L = c->L;
+    const size_t es = c->esM;
+    const int64_t rows = L.py * (L.nz + 1), w = L.nx + 1;
+    char *dev = (char *)dev_field + L.ox * es;
+    if (to_dev) {
+        HIPTRY(hipMemcpy2DAsync(dev, L.px * es, user, w * es, w * es, rows,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    } else {
+        HIPTRY(hipMemcpy2DAsync(user, w * es, dev, L.px * es, w * es, rows,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    }
+    if (!on_device) HIPTRY(hipStreamSynchronize(c->stream));
+    return NLSE_OK;
+}
+
+static int read_scalars(nlse_ctx *c, double *dst, int count)
+{
+    HIPTRY(hipMemcpyAsync(dst, c->red + 2 * reduce_partials(), count * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPTRY(hipStreamSynchronize(c->stream));
+    return NLSE_OK;
+}
+
+// Nodes 0..3 and n-3..n of a 1D field, converted to complex double on the host.
+static int host_edges_1d(nlse_ctx *c, double out[8][2])
+{
+    const int64_t n = c->L.nx;
+    const int64_t idx[8] = {0, 1, 2, 3, n - 3, n - 2, n - 1, n};
+    for (int k = 0; k < 8; ++k) {
+        unsigned char buf[16];
+        HIPTRY(hipMemcpyAsync(buf, (char *)c->psi + (c->L.ox + idx[k]) * c->esM, c->esM, hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPTRY(hipStreamSynchronize(c->stream));
+        if (c->esM == 16) {
+            out[k][0] = ((double *)buf)[0];
+            out[k][1] = ((double *)buf)[1];
+        } else {
+            out[k][0] = ((float *)buf)[0];
+            out[k][1] = ((float *)buf)[1];
+        }
+    }
+    return NLSE_OK;
+}
+
+// MSD closure values at one end of a 1D field (host, FP64), from nodes b, b-1, b-2, b-3
+// in u[0..3]: returns D_b (Eq. msdbc_lap) and F_{b-1}.
+static void msd_end(const nlse_ctx *c, const double u[4][2], const double Vq[4], double Db[2], double Fbm1[2])
+{
+    const double ih2 = 1.0 / (c->p.h * c->p.h), a = c->p.a, s = c->p.s;
+    auto d2 = [&](int i, double r[2]) {   // second difference at u[i] (neighbours u[i-1], u[i+1])
+        r[0] = ih2 * ((u[i - 1][0] - 2.0 * u[i][0]) + u[i + 1][0]);
+        r[1] = ih2 * ((u[i - 1][1] - 2.0 * u[i][1]) + u[i + 1][1]);
+    };
+    auto N = [&](int i) { return s * (u[i][0] * u[i][0] + u[i][1] * u[i][1]) - Vq[i]; };
+    double D1[2], D2[2];
+    d2(1, D1);
+    d2(2, D2);
+    const double den = u[1][0] * u[1][0] + u[1][1] * u[1][1];
+    const double ratio = den != 0.0 ? (D1[0] * u[1][0] + D1[1] * u[1][1]) / den : 0.0;
+    const double f = ratio + (N(1) - N(0)) / a;
+    Db[0] = f * u[0][0];
+    Db[1] = f * u[0][1];
+    const double lap[2] = {7.0 / 6.0 * D1[0] - (D2[0] + Db[0]) / 12.0, 7.0 / 6.0 * D1[1] - (D2[1] + Db[1]) / 12.0};
+    const double z[2] = {a * lap[0] + N(1) * u[1][0], a * lap[1] + N(1) * u[1][1]};
+    Fbm1[0] = -z[1];
+    Fbm1[1] = z[0];
+}
+
+int nlse_max_dt(nlse_ctx *c, double *out)
+{
+    if (!c || !out) return fail(NLSE_E_INVAL, "nlse_max_dt: NULL argument");
+    HIPTRY(launch_minmax_nonlin(c->prec, c->psi, c->V, c->L, c->p.s, c->red, c->red + 2 * reduce_partials(),
+                                c->stream));
+    double mm[2];
+    int rc = read_scalars(c, mm, 2);
+    if (rc) return rc;
+    if (!std::isfinite(mm[0]) || !std::isfinite(mm[1])) return fail(NLSE_E_NONFINITE, "field is not finite");
+    static const double gmax[3] = {64.0 / 12.0, 128.0 / 12.0, 192.0 / 12.0};
+    static const double gmin[3] = {-4.0 / 12.0, -8.0 / 12.0, -12.0 / 12.0};
+    const double h2a = c->p.h * c->p.h / c->p.a;
+    const double lmin = h2a * mm[0], lmax = h2a * mm[1];
+    double m = std::fmax(gmax[c->p.ndim - 1] - lmin, lmax - gmin[c->p.ndim - 1]);
+    if (c->p.bc == NLSE_BC_MSD) {
+        double e[8][2];
+        rc = host_edges_1d(c, e);
+        if (rc) return rc;
+        const int64_t n = c->L.nx;
+        auto Vh = [&](int64_t i) { return c->Vhost.empty() ? 0.0 : c->Vhost[(size_t)i]; };
+        const double lo[4][2] = {{e[0][0], e[0][1]}, {e[1][0], e[1][1]}, {e[2][0], e[2][1]}, {e[3][0], e[3][1]}};
+        const double hi[4][2] = {{e[7][0], e[7][1]}, {e[6][0], e[6][1]}, {e[5][0], e[5][1]}, {e[4][0], e[4][1]}};
+        const double vlo[4] = {Vh(0), Vh(1), Vh(2), Vh(3)}, vhi[4] = {Vh(n), Vh(n - 1), Vh(n - 2), Vh(n - 3)};
+        for (int side = 0; side < 2; ++side) {
+            double Db[2], F1[2];
+            const double(*u)[2] = side ? hi : lo;
+            msd_end(c, u, side ? vhi : vlo, Db, F1);
+            const double den = u[1][0] * u[1][0] + u[1][1] * u[1][1];
+            if (den != 0.0) m = std::fmax(m, h2a * std::sqrt((F1[0] * F1[0] + F1[1] * F1[1]) / den));
+        }
+    }
+    *out = std::sqrt(8.0) * c->p.h * c->p.h / (c->p.a * m);
+    return NLSE_OK;
+}
+
+int nlse_set_field(nlse_ctx *c, const void *psi, int on_device)
+{
+    if (!c || !psi) return fail(NLSE_E_INVAL, "nlse_set_field: NULL argument");
+    int rc = copy_field(c, c->psi, (void *)psi, on_device, true);
+    if (rc) return rc;
+    if (c->p.ndim > 1) {
+        HIPTRY(launch_master_to_stage(c->prec, c->psi, c->A, c->L, c->stream));
+        HIPTRY(launch_master_to_stage(c->prec, c->psi, c->B, c->L, c->stream));
+        Coeffs co = base_coeffs(c->p);
+        HIPTRY(launch_boundary_d(c->prec, c->psi, c->V, c->L, co, c->DB, c->stream));
+    }
+    c->have_field = true;
+    double k;
+    rc = nlse_max_dt(c, &k);
+    if (rc) return rc;
+    c->kmax = k;
+    return NLSE_OK;
+}
+
+int nlse_get_field(nlse_ctx *c, void *out, int on_device)
+{
+    if (!c || !out) return fail(NLSE_E_INVAL, "nlse_get_field: NULL argument");
+    return copy_field(c, c->psi, out, on_device, false);
+}
+
+int nlse_step(nlse_ctx *c, int64_t nsteps, double dt)
+{
+    if (!c) return fail(NLSE_E_INVAL, "NULL context");
+    if (nsteps < 0) return fail(NLSE_E_INVAL, "nsteps must be >= 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(NLSE_E_INVAL, "dt must be > 0");
+    if (!c->have_field) return fail(NLSE_E_INVAL, "no field set");
+    if (!c->p.allow_unstable && dt > c->kmax) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "dt = %.17g exceeds the stability bound %.17g", dt, c->kmax);
+        return fail(NLSE_E_DT_UNSTABLE, buf);
+    }
+    if (nsteps == 0) return NLSE_OK;
+    Coeffs co = base_coeffs(c->p);
+    if (c->p.ndim == 1) {
+        Solve1DArgs a;
+        a.psin = c->psi;
+        a.V = c->V;
+        a.L = c->L;
+        a.c = co;
+        a.k = dt;
+        a.k2 = dt / 2.0;
+        a.k6 = dt / 6.0;
+        a.nsteps = nsteps;
+        a.msd = c->p.bc == NLSE_BC_MSD;
+        HIPTRY(launch_solve1d(c->prec, a, c->stream));
+        return NLSE_OK;
+    }
+    const double ck[4] = {dt / 2.0, dt / 2.0, dt, dt / 6.0};
+    void *ins[4] = {c->psi, c->A, c->B, c->A};
+    void *outs[4] = {c->A, c->B, c->A, nullptr};
+    for (int64_t step = 0; step < nsteps; ++step) {
+        for (int st = 0; st < 4; ++st) {
+            StageArgs a;
+            a.in = ins[st];
+            a.out = outs[st];
+            a.psin = c->psi;
+            a.K = c->K;
+            a.V = c->V;
+            for (int d = 0; d < 3; ++d) a.DB[d] = c->DB[d];
+            a.L = c->L;
+            a.c = co;
+            a.c.ck = ck[st];
+            a.stage = st + 1;
+            hipError_t e = c->p.ndim == 2 ? launch_stage2d(c->prec, a, c->stream)
+                                          : launch_stage3d(c->prec, a, c->stream);
+            if (e != hipSuccess) return hipfail(e, "stage kernel launch");
+        }
+    }
+    return NLSE_OK;
+}
+
+int nlse_mass(nlse_ctx *c, double *out)
+{
+    if (!c || !out) return fail(NLSE_E_INVAL, "nlse_mass: NULL argument");
+    HIPTRY(launch_mass(c->prec, c->psi, c->L, c->red, c->red + 2 * reduce_partials(), c->stream));
+    double m;
+    int rc = read_scalars(c, &m, 1);
+    if (rc) return rc;
+    *out = std::pow(c->p.h, c->p.ndim) * m;
+    if (!std::isfinite(*out)) return fail(NLSE_E_NONFINITE, "mass is not finite");
+    return NLSE_OK;
+}
+
+int nlse_energy(nlse_ctx *c, double *out)
+{
+    if (!c || !out) return fail(NLSE_E_INVAL, "nlse_energy: NULL argument");
+    Coeffs co = base_coeffs(c->p);
+    if (c->p.ndim == 1) {
+        // boundary closure of the current field (Dirichlet Eq. dbc_lap or MSD Eq. msdbc_lap)
+        double e[8][2];
+        int rc = host_edges_1d(c, e);
+        if (rc) return rc;
+        const int64_t n = c->L.nx;
+        auto Vh = [&](int64_t i) { return c->Vhost.empty() ? 0.0 : c->Vhost[(size_t)i]; };
+        double db[2][2];
+        const int ends[2] = {0, 7};
+        for (int side = 0; side < 2; ++side) {
+            const double *ub = e[ends[side]];
+            if (c->p.bc == NLSE_BC_MSD) {
+                const double lo[4][2] = {{e[0][0], e[0][1]}, {e[1][0], e[1][1]}, {e[2][0], e[2][1]}, {e[3][0], e[3][1]}};
+                const double hi[4][2] = {{e[7][0], e[7][1]}, {e[6][0], e[6][1]}, {e[5][0], e[5][1]}, {e[4][0], e[4][1]}};
+                const double vlo[4] = {Vh(0), Vh(1), Vh(2), Vh(3)}, vhi[4] = {Vh(n), Vh(n - 1), Vh(n - 2), Vh(n - 3)};
+                double F1[2];
+                msd_end(c, side ? hi : lo, side ? vhi : vlo, db[side], F1);
+            } else {
+                const double N = c->p.s * (ub[0] * ub[0] + ub[1] * ub[1]) - Vh(side ? n : 0);
+                db[side][0] = -N * ub[0] / c->p.a;
+                db[side][1] = -N * ub[1] / c->p.a;
+            }
+        }
+        double tmpd[4] = {db[0][0], db[0][1], db[1][0], db[1][1]};
+        float tmpf[4] = {(float)db[0][0], (float)db[0][1], (float)db[1][0], (float)db[1][1]};
+        const void *src = c->esR == 16 ? (const void *)tmpd : (const void *)tmpf;
+        HIPTRY(hipMemcpyAsync(c->DB[0], src, c->esR == 16 ? sizeof tmpd : sizeof tmpf, hipMemcpyHostToDevice,
+                              c->stream));
+        HIPTRY(hipStreamSynchronize(c->stream));
+    }
+    const void *db[3] = {c->DB[0], c->DB[1], c->DB[2]};
+    HIPTRY(launch_energy(c->prec, c->psi, c->V, db, c->L, co, c->red, c->red + 2 * reduce_partials(), c->stream));
+    double e;
+    int rc = read_scalars(c, &e, 1);
+    if (rc) return rc;
+    *out = e;
+    if (!std::isfinite(e)) return fail(NLSE_E_NONFINITE, "energy is not finite");
+    return NLSE_OK;
+}
+
+}  // extern "C"

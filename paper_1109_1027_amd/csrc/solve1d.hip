@@ -1,0 +1,175 @@
+// Persistent 1D 2SHOC-RK4 solver: one workgroup keeps the whole field on chip
+// and runs every RK4 step of the call in a single launch.
+//
+// Per stage (Sec. 2.1 Eqs. 2shoc1d-2shoc1d2, Sec. 3.1-3.2):
+//   phase A  D_i = (Psi_{i+1} - 2 Psi_i + Psi_{i-1}) / h^2 on interior nodes (LDS);
+//            boundary D_b: Dirichlet Eq. dbc_lap, or MSD Eq. msdbc_lap, which needs
+//            D_{b-1}: the owner of the boundary node recomputes it from Psi.
+//   phase B  Lap_i = (7/6) D_i - (1/12)(D_{i+1} + D_{i-1});  F_i = i[a Lap_i + (s|Psi_i|^2 - V_i) Psi_i];
+//            boundary F_b: Dirichlet 0 (Eq. dbc_ut); MSD i Im(F_{b-1}/Psi_{b-1}) Psi_b (Eq. msdbc_ut),
+//            with F_{b-1} recomputed by the boundary owner (interior first, boundary second).
+//   phase C  the RK4 array operations of the stage; the next stage field is written to LDS.
+// Psi^n (master precision), K_tot and V stay in registers of the owning thread for
+// the whole launch; LDS holds the stage field and D.  HBM is touched only to load
+// Psi^n at the start and store it at the end.
+#include "kernels.h"
+
+namespace nlse {
+
+template <typename R> struct NPT1D;
+template <> struct NPT1D<double> { static constexpr int v = 5; };   // 5 x 1024 nodes x 32 B = 160 KiB
+template <> struct NPT1D<float> { static constexpr int v = 9; };    // 9 x 1024 nodes x 16 B = 144 KiB
+
+constexpr int BS1D = 1024;
+
+template <typename R, typename M>
+__device__ __forceinline__ C<R> lap1d(const C<R> *sD, int64_t i, R c76, R c112)
+{
+    return csub<R>(cscale<R>(c76, sD[i]), cscale<R>(c112, cadd<R>(sD[i + 1], sD[i - 1])));
+}
+
+template <typename R, typename M>
+__global__ __launch_bounds__(BS1D) void solve1d_kernel(Solve1DArgs A)
+{
+    constexpr int NPT = NPT1D<R>::v;
+    extern __shared__ unsigned char smem_raw[];
+    const int64_t n = A.L.nx;                 // nodes 0..n
+    C<R> *sin = (C<R> *)smem_raw;             // stage field
+    C<R> *sD = sin + (n + 1);                 // step-1 array
+    const int t = threadIdx.x;
+    const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
+    const R ia = (R)A.c.ia, two = (R)2;
+    const R k2 = (R)A.k2, kk = (R)A.k, k6 = (R)A.k6;
+    const bool msd = A.msd != 0;
+    C<M> *gpsi = (C<M> *)A.psin;
+    const R *gV = (const R *)A.V;
+    const int64_t o = A.L.ox;
+
+    C<M> pn[NPT];
+    C<R> kt[NPT], F[NPT];
+    R vv[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int64_t i = t + (int64_t)j * BS1D;
+        pn[j] = mk<M>(M(0), M(0));
+        kt[j] = czero<R>();
+        F[j] = czero<R>();
+        vv[j] = R(0);
+        if (i <= n) {
+            pn[j] = gpsi[o + i];
+            vv[j] = gV ? gV[o + i] : R(0);
+            sin[i] = cvt<R, M>(pn[j]);
+        }
+    }
+    auto Vat = [&](int64_t i) -> R { return gV ? gV[o + i] : R(0); };
+    auto nonl = [&](int64_t i) -> R { const C<R> u = sin[i]; return s * (u.x * u.x + u.y * u.y) - Vat(i); };
+    // second difference at an interior node straight from the stage field
+    auto d2 = [&](int64_t i) -> C<R> {
+        return cscale<R>(ih2, cadd<R>(csub<R>(sin[i + 1], cscale<R>(two, sin[i])), sin[i - 1]));
+    };
+    // F at an interior node from D in LDS
+    auto Fat = [&](int64_t i) -> C<R> {
+        const C<R> u = sin[i];
+        const C<R> z = cadd<R>(cscale<R>(a, lap1d<R, M>(sD, i, c76, c112)), cscale<R>(nonl(i), u));
+        return mk<R>(-z.y, z.x);
+    };
+
+    for (int64_t step = 0; step < A.nsteps; ++step) {
+        for (int stage = 1; stage <= 4; ++stage) {
+            __syncthreads();
+            // phase A: step 1 with its boundary closure
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const int64_t i = t + (int64_t)j * BS1D;
+                if (i > n) continue;
+                if (i > 0 && i < n) {
+                    sD[i] = d2(i);
+                } else {
+                    const int64_t bm1 = (i == 0) ? 1 : n - 1;
+                    const C<R> ub = sin[i];
+                    if (!msd) {
+                        sD[i] = cscale<R>(-nonl(i) * ia, ub);
+                    } else {
+                        const C<R> ui = sin[bm1], Di = d2(bm1);
+                        const R den = ui.x * ui.x + ui.y * ui.y;
+                        const R ratio = den != R(0) ? (Di.x * ui.x + Di.y * ui.y) / den : R(0);
+                        sD[i] = cscale<R>(ratio + (nonl(bm1) - nonl(i)) * ia, ub);
+                    }
+                }
+            }
+            __syncthreads();
+            // phase B: step 2 and F
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const int64_t i = t + (int64_t)j * BS1D;
+                F[j] = czero<R>();
+                if (i > n) continue;
+                if (i > 0 && i < n) {
+                    F[j] = Fat(i);
+                } else if (msd) {
+                    const int64_t bm1 = (i == 0) ? 1 : n - 1;
+                    const C<R> Fi = Fat(bm1), ui = sin[bm1], ub = sin[i];
+                    const R den = ui.x * ui.x + ui.y * ui.y;
+                    const R im = den != R(0) ? (Fi.y * ui.x - Fi.x * ui.y) / den : R(0);
+                    F[j] = mk<R>(-im * ub.y, im * ub.x);
+                }
+            }
+            __syncthreads();
+            // phase C: RK4 array operations of this stage
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const int64_t i = t + (int64_t)j * BS1D;
+                if (i > n) continue;
+                if ((i == 0 || i == n) && !msd) continue;   // Dirichlet nodes never change
+                C<R> nxt;
+                if (stage == 1) {
+                    kt[j] = F[j];
+                    const C<R> inc = cscale<R>(k2, F[j]);
+                    nxt = cvt<R, M>(mk<M>(pn[j].x + (M)inc.x, pn[j].y + (M)inc.y));
+                } else if (stage <= 3) {
+                    kt[j] = cadd<R>(kt[j], cscale<R>(two, F[j]));
+                    const C<R> inc = cscale<R>(stage == 2 ? k2 : kk, F[j]);
+                    nxt = cvt<R, M>(mk<M>(pn[j].x + (M)inc.x, pn[j].y + (M)inc.y));
+                } else {
+                    const C<R> inc = cscale<R>(k6, cadd<R>(kt[j], F[j]));
+                    pn[j] = mk<M>(pn[j].x + (M)inc.x, pn[j].y + (M)inc.y);
+                    nxt = cvt<R, M>(pn[j]);
+                }
+                sin[i] = nxt;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int64_t i = t + (int64_t)j * BS1D;
+        if (i <= n) gpsi[o + i] = pn[j];
+    }
+}
+
+int64_t solve1d_max_nodes(Prec prec)
+{
+    return (int64_t)BS1D * (prec == P_F64 ? NPT1D<double>::v : NPT1D<float>::v);
+}
+
+template <typename R, typename M>
+static hipError_t launch1d(const Solve1DArgs &a, hipStream_t st)
+{
+    const size_t lds = 2 * sizeof(C<R>) * (size_t)(a.L.nx + 1);
+    // a launch that asks for more LDS than the device has fails with an error code
+    (void)hipFuncSetAttribute((const void *)solve1d_kernel<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL((solve1d_kernel<R, M>), dim3(1), dim3(BS1D), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve1d(Prec prec, const Solve1DArgs &a, hipStream_t st)
+{
+    if (a.L.nx + 1 > solve1d_max_nodes(prec)) return hipErrorInvalidValue;
+    switch (prec) {
+    case P_F64: return launch1d<double, double>(a, st);
+    case P_F32: return launch1d<float, float>(a, st);
+    default: return launch1d<float, double>(a, st);
+    }
+}
+
+}  // namespace nlse

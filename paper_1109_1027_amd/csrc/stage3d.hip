@@ -1,0 +1,201 @@
+// Fused RK4-stage kernel for the 3D NLSE with the per-axis 2SHOC Laplacian
+// (Sec. 2.3 Eqs. 3d2shocMs1-2, Sec. 3.1):
+//   step 1   D^a = delta_a^2 Psi,  a in {x, y, z}
+//   step 2   Lap = sum_a [ (7/6) D^a - (1/12)(D^a_{+a} + D^a_{-a}) ]
+//   then F = i[a Lap + (s|Psi|^2 - V) Psi] and the stage's RK4 array operations.
+//
+// 2.5D scheme: a block owns a 64 x TYB column tile (x fastest, one coalesced row
+// segment per wave) and marches along z through TZ planes.  Each thread keeps its
+// column's Psi at z-2..z+2 and D^z at z-1..z+1 in registers; the current plane of
+// Psi (with a 2-node halo in x and y) and the in-plane D^x, D^y (with a 1-node
+// halo) go through LDS.  No D value is ever written to global memory.
+//
+// Face closure values D^a_b (boundary-face nodes) are the Dirichlet constants of
+// launch_boundary_d; see stage2d.hip for why the per-axis and single-storage
+// forms then coincide.
+#include "kernels.h"
+
+namespace nlse {
+
+template <typename T, typename U> struct same3_t { static constexpr bool v = false; };
+template <typename T> struct same3_t<T, T> { static constexpr bool v = true; };
+
+template <typename IN, typename R, typename M, int TYB, int TZ>
+__global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int64_t tiles_x, int64_t tiles_y)
+{
+    constexpr int W = 64, NT = 64 * TYB;
+    static_assert(NT >= 4 * W, "y-halo load needs at least 256 threads");
+    __shared__ C<R> sp[TYB + 4][W + 4];
+    __shared__ C<R> sdx[TYB][W + 2];
+    __shared__ C<R> sdy[TYB + 2][W];
+
+    const int t = threadIdx.x, tx = t & 63, ty = t >> 6;
+    const Layout L = A.L;
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t bx = lb % tiles_x, by = (lb / tiles_x) % tiles_y, bz = lb / (tiles_x * tiles_y);
+    const int64_t x0 = 1 + W * bx, y0 = 1 + TYB * by, z0 = 1 + TZ * bz;
+    const int64_t x = x0 + tx, y = y0 + ty;
+    const bool col_ok = x <= L.nx && y <= L.ny;
+    const bool upd_col = x < L.nx && y < L.ny;
+
+    const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
+    const R ck = (R)A.c.ck, two = (R)2;
+    const int stage = A.stage;
+    const C<IN> *in = (const C<IN> *)A.in;
+    const C<R> *DBx = (const C<R> *)A.DB[0];
+    const C<R> *DBy = (const C<R> *)A.DB[1];
+    const C<R> *DBz = (const C<R> *)A.DB[2];
+    const R *V = (const R *)A.V;
+    C<M> *psin = (C<M> *)A.psin;
+    C<R> *K = (C<R> *)A.K;
+    C<R> *out = (C<R> *)A.out;
+    constexpr bool in_is_r = same3_t<IN, R>::v;
+    const int64_t fx = (L.nz + 1) * (L.ny + 1), fy = (L.nz + 1) * (L.nx + 1), fz = (L.ny + 1) * (L.nx + 1);
+
+    auto ld = [&](int64_t xx, int64_t yy, int64_t zz) -> C<R> {
+        if (xx < 0 || xx > L.nx || yy < 0 || yy > L.ny || zz < 0 || zz > L.nz) return czero<R>();
+        return cvt<R, IN>(in[L.idx(xx, yy, zz)]);
+    };
+    auto d2 = [&](const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> {
+        return cscale<R>(ih2, cadd<R>(csub<R>(p, cscale<R>(two, c)), m));
+    };
+    // D^z at plane zz of the own column from the queue values, or the face closure
+    auto dz_at = [&](int64_t zz, const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> {
+        if (!col_ok) return czero<R>();
+        if (zz == 0) return DBz[y * (L.nx + 1) + x];
+        if (zz == L.nz) return DBz[fz + y * (L.nx + 1) + x];
+        return d2(m, c, p);
+    };
+
+    // register queue: q[k] = Psi(z - 2 + k) of the own column
+    C<R> q[5];
+    q[0] = col_ok ? ld(x, y, z0 - 2) : czero<R>();
+    q[1] = col_ok ? ld(x, y, z0 - 1) : czero<R>();
+    q[2] = col_ok ? ld(x, y, z0) : czero<R>();
+    q[3] = col_ok ? ld(x, y, z0 + 1) : czero<R>();
+    C<R> dzm = dz_at(z0 - 1, q[0], q[1], q[2]);
+    C<R> dz0 = dz_at(z0, q[1], q[2], q[3]);
+
+    for (int zi = 0; zi < TZ; ++zi) {
+        const int64_t z = z0 + zi;
+        if (z >= L.nz) break;   // block-uniform
+        q[4] = col_ok ? ld(x, y, z + 2) : czero<R>();
+        // halo of plane z: x-halo (4 columns x TYB rows), y-halo (4 rows x 64 columns)
+        C<R> hx = czero<R>(), hy = czero<R>();
+        if (t < 4 * TYB) {
+            const int r = t >> 2, k = t & 3;
+            hx = ld(x0 + (k == 0 ? -2 : k == 1 ? -1 : k == 2 ? W : W + 1), y0 + r, z);
+        }
+        if (t < 4 * W) {
+            const int k = t >> 6, c = t & 63;
+            hy = ld(x0 + c, y0 + (k == 0 ? -2 : k == 1 ? -1 : k == 2 ? TYB : TYB + 1), z);
+        }
+        // update operands of plane z
+        const bool upd = upd_col && z < L.nz;
+        const int64_t p = L.idx(x, y, z);
+        C<M> pn = mk<M>(M(0), M(0));
+        C<R> kt = czero<R>();
+        R vv = R(0);
+        if (upd && (stage >= 2 || !in_is_r)) pn = psin[p];
+        if (upd && stage >= 2) kt = K[p];
+        if (upd && V) vv = V[p];
+        const C<R> dzp = dz_at(z + 1, q[2], q[3], q[4]);
+
+        sp[ty + 2][tx + 2] = q[2];
+        if (t < 4 * TYB) {
+            const int r = t >> 2, k = t & 3;
+            sp[r + 2][k == 0 ? 0 : k == 1 ? 1 : k == 2 ? W + 2 : W + 3] = hx;
+        }
+        if (t < 4 * W) {
+            const int k = t >> 6, c = t & 63;
+            sp[k == 0 ? 0 : k == 1 ? 1 : k == 2 ? TYB + 2 : TYB + 3][c + 2] = hy;
+        }
+        __syncthreads();
+        // step 1 in-plane: own D^x, D^y and the one-node halos
+        C<R> dx = d2(sp[ty + 2][tx + 1], sp[ty + 2][tx + 2], sp[ty + 2][tx + 3]);
+        C<R> dy = d2(sp[ty + 1][tx + 2], sp[ty + 2][tx + 2], sp[ty + 3][tx + 2]);
+        if (col_ok && x == L.nx) dx = DBx[fx + z * (L.ny + 1) + y];
+        if (col_ok && y == L.ny) dy = DBy[fy + z * (L.nx + 1) + x];
+        C<R> hdx = czero<R>(), hdy = czero<R>();
+        if (t < 2 * TYB) {
+            const int r = t >> 1, side = t & 1;
+            const int c = side ? W + 2 : 1;
+            hdx = d2(sp[r + 2][c - 1], sp[r + 2][c], sp[r + 2][c + 1]);
+            const int64_t hxx = side ? x0 + W : x0 - 1, yy = y0 + r;
+            if (yy <= L.ny) {
+                if (hxx == 0) hdx = DBx[z * (L.ny + 1) + yy];
+                else if (hxx == L.nx) hdx = DBx[fx + z * (L.ny + 1) + yy];
+            }
+        }
+        if (t < 2 * W) {
+            const int side = t >> 6, c = t & 63;
+            const int r = side ? TYB + 2 : 1;
+            hdy = d2(sp[r - 1][c + 2], sp[r][c + 2], sp[r + 1][c + 2]);
+            const int64_t yy = side ? y0 + TYB : y0 - 1, xx = x0 + c;
+            if (xx <= L.nx) {
+                if (yy == 0) hdy = DBy[z * (L.nx + 1) + xx];
+                else if (yy == L.ny) hdy = DBy[fy + z * (L.nx + 1) + xx];
+            }
+        }
+        __syncthreads();
+        sdx[ty][tx + 1] = dx;
+        sdy[ty + 1][tx] = dy;
+        if (t < 2 * TYB) sdx[t >> 1][(t & 1) ? W + 1 : 0] = hdx;
+        if (t < 2 * W) sdy[(t >> 6) ? TYB + 1 : 0][t & 63] = hdy;
+        __syncthreads();
+        if (upd) {
+            const C<R> nb = cadd<R>(cadd<R>(cadd<R>(sdx[ty][tx + 2], sdx[ty][tx]), cadd<R>(sdy[ty + 2][tx], sdy[ty][tx])),
+                                    cadd<R>(dzp, dzm));
+            const C<R> lap = csub<R>(cscale<R>(c76, cadd<R>(cadd<R>(dx, dy), dz0)), cscale<R>(c112, nb));
+            const C<R> u = q[2];
+            const R nl = s * (u.x * u.x + u.y * u.y) - vv;
+            const C<R> zz = cadd<R>(cscale<R>(a, lap), cscale<R>(nl, u));
+            const C<R> F = mk<R>(-zz.y, zz.x);
+            if (stage == 1) {
+                const C<M> base = in_is_r ? cvt<M, R>(u) : pn;
+                K[p] = F;
+                const C<R> inc = cscale<R>(ck, F);
+                out[p] = cvt<R, M>(mk<M>(base.x + (M)inc.x, base.y + (M)inc.y));
+            } else if (stage <= 3) {
+                K[p] = cadd<R>(kt, cscale<R>(two, F));
+                const C<R> inc = cscale<R>(ck, F);
+                out[p] = cvt<R, M>(mk<M>(pn.x + (M)inc.x, pn.y + (M)inc.y));
+            } else {
+                const C<R> inc = cscale<R>(ck, cadd<R>(kt, F));
+                psin[p] = mk<M>(pn.x + (M)inc.x, pn.y + (M)inc.y);
+            }
+        }
+        q[0] = q[1];
+        q[1] = q[2];
+        q[2] = q[3];
+        q[3] = q[4];
+        dzm = dz0;
+        dz0 = dzp;
+    }
+}
+
+template <typename IN, typename R, typename M, int TYB, int TZ>
+static hipError_t launch3(const StageArgs &a, hipStream_t st)
+{
+    const int64_t tiles_x = (a.L.nx - 1 + 63) / 64;
+    const int64_t tiles_y = (a.L.ny - 1 + TYB - 1) / TYB;
+    const int64_t tiles_z = (a.L.nz - 1 + TZ - 1) / TZ;
+    const int64_t blocks = tiles_x * tiles_y * tiles_z;
+    hipLaunchKernelGGL((stage3d_kernel<IN, R, M, TYB, TZ>), dim3((unsigned)blocks), dim3(64 * TYB), 0, st, a,
+                       tiles_x, tiles_y);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage3d(Prec prec, const StageArgs &a, hipStream_t st)
+{
+    constexpr int TYB = 4, TZ = 32;
+    switch (prec) {
+    case P_F64: return launch3<double, double, double, TYB, TZ>(a, st);
+    case P_F32: return launch3<float, float, float, TYB, TZ>(a, st);
+    default:
+        if (a.stage == 1) return launch3<double, float, double, TYB, TZ>(a, st);
+        return launch3<float, float, double, TYB, TZ>(a, st);
+    }
+}
+
+}  // namespace nlse

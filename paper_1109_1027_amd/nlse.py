@@ -1,0 +1,189 @@
+"""ctypes binding of the gfx950 2SHOC-RK4 library (C ABI in include/nlse.h).
+
+Argument marshalling only: every numerical step runs in the HIP kernels of
+``libnlse_hip.so``.  There is no CPU path; if the library is missing the import
+fails.  PyTorch, when used, only provides device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnlse_hip.so")
+
+OK, E_INVAL, E_DT_UNSTABLE, E_NONFINITE, E_NOMEM, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+PREC = {"f64": 0, "f32": 1, "mixed": 2}
+BC = {"dirichlet": 0, "msd": 1}
+_STATUS = {E_INVAL: "NLSE_E_INVAL", E_DT_UNSTABLE: "NLSE_E_DT_UNSTABLE", E_NONFINITE: "NLSE_E_NONFINITE",
+           E_NOMEM: "NLSE_E_NOMEM", E_HIP: "NLSE_E_HIP", E_UNSUPPORTED: "NLSE_E_UNSUPPORTED"}
+
+
+class NLSEError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 3), ("h", ctypes.c_double),
+                ("a", ctypes.c_double), ("s", ctypes.c_double), ("V", ctypes.POINTER(ctypes.c_double)),
+                ("bc", ctypes.c_int32), ("prec", ctypes.c_int32), ("allow_unstable", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+EXPORTS = ["nlse_create", "nlse_set_field", "nlse_step", "nlse_get_field", "nlse_mass", "nlse_energy",
+           "nlse_max_dt", "nlse_sync", "nlse_destroy", "nlse_last_error", "nlse_launches_per_step"]
+
+_lib = None
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1109_1027_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
+    L.nlse_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params)]
+    L.nlse_set_field.argtypes = [vp, vp, ctypes.c_int]
+    L.nlse_step.argtypes = [vp, i64, dbl]
+    L.nlse_get_field.argtypes = [vp, vp, ctypes.c_int]
+    for f in ("nlse_mass", "nlse_energy", "nlse_max_dt"):
+        getattr(L, f).argtypes = [vp, ctypes.POINTER(dbl)]
+    L.nlse_sync.argtypes = [vp]
+    L.nlse_destroy.argtypes = [vp]
+    L.nlse_destroy.restype = None
+    L.nlse_last_error.restype = ctypes.c_char_p
+    L.nlse_launches_per_step.argtypes = [vp]
+    for f in EXPORTS:
+        if f not in ("nlse_destroy", "nlse_last_error"):
+            getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != OK:
+        raise NLSEError(rc, load().nlse_last_error().decode())
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except ImportError:
+        pass
+    return None
+
+
+class Solver:
+    """One NLSE problem on the GPU: i Psi_t + a Lap Psi - V Psi + s|Psi|^2 Psi = 0.
+
+    n: intervals per axis (int or sequence), h: grid step, V: potential on all nodes
+    (numpy, field order [z][y][x]) or None, bc: "dirichlet" | "msd" (1D),
+    prec: "f64" | "f32" | "mixed".  Fields are complex128 ("f64", "mixed") or
+    complex64 ("f32"), all (n+1)^d nodes including the boundary."""
+
+    def __init__(self, ndim, n, h, a, s, V=None, bc="dirichlet", prec="f64", allow_unstable=False,
+                 stream="current"):
+        L = load()
+        nn = tuple(int(v) for v in (n if hasattr(n, "__len__") else (n,) * ndim))
+        self.ndim, self.n, self.h, self.a, self.s = int(ndim), nn, float(h), float(a), float(s)
+        self.prec, self.bc = prec, bc
+        self.shape = tuple(v + 1 for v in reversed(nn[:ndim]))
+        self.dtype = np.complex64 if prec == "f32" else np.complex128
+        p = Params()
+        p.ndim = self.ndim
+        for i in range(3):
+            p.n[i] = nn[i] if i < ndim else 0
+        p.h, p.a, p.s = self.h, self.a, self.s
+        self._V = None
+        if V is not None:
+            self._V = np.ascontiguousarray(V, dtype=np.float64)
+            if self._V.size != int(np.prod(self.shape)):
+                raise ValueError("V must hold one value per node")
+            p.V = self._V.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.bc = BC[bc]
+        p.prec = PREC[prec]
+        p.allow_unstable = int(bool(allow_unstable))
+        self.stream = _current_stream() if stream == "current" else stream
+        p.stream = self.stream
+        h_ = ctypes.c_void_p()
+        _check(L.nlse_create(ctypes.byref(h_), ctypes.byref(p)))
+        self._h = h_
+
+    @classmethod
+    def from_spec(cls, spec, prec="f64", **kw):
+        g = spec.grid
+        return cls(g.dim, g.n, g.h, spec.a, spec.s, spec.V, spec.bc, prec, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().nlse_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- fields
+    def set_field(self, psi):
+        """psi: numpy array (host) or torch tensor on the GPU, all nodes, field dtype."""
+        if _is_torch(psi):
+            self._check_tensor(psi)
+            _check(load().nlse_set_field(self._h, ctypes.c_void_p(psi.data_ptr()), 1))
+        else:
+            arr = np.ascontiguousarray(psi, dtype=self.dtype).reshape(self.shape)
+            _check(load().nlse_set_field(self._h, arr.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def get_field(self, out=None):
+        """Return the field as numpy, or copy it into the given GPU torch tensor."""
+        if out is not None and _is_torch(out):
+            self._check_tensor(out)
+            _check(load().nlse_get_field(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        arr = np.empty(self.shape, dtype=self.dtype)
+        _check(load().nlse_get_field(self._h, arr.ctypes.data_as(ctypes.c_void_p), 0))
+        return arr
+
+    def _check_tensor(self, t):
+        import torch
+        want = torch.complex64 if self.dtype == np.complex64 else torch.complex128
+        if t.dtype != want or not t.is_cuda or not t.is_contiguous() or t.numel() != int(np.prod(self.shape)):
+            raise ValueError(f"tensor must be a contiguous {want} GPU tensor with {int(np.prod(self.shape))} elements")
+
+    # ---- time stepping and diagnostics
+    def step(self, nsteps, dt):
+        _check(load().nlse_step(self._h, int(nsteps), float(dt)))
+
+    def sync(self):
+        _check(load().nlse_sync(self._h))
+
+    def _scalar(self, fn):
+        v = ctypes.c_double()
+        _check(fn(self._h, ctypes.byref(v)))
+        return v.value
+
+    def mass(self):
+        return self._scalar(load().nlse_mass)
+
+    def energy(self):
+        return self._scalar(load().nlse_energy)
+
+    def max_dt(self):
+        return self._scalar(load().nlse_max_dt)
+
+    def launches_per_step(self):
+        return load().nlse_launches_per_step(self._h)
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")

@@ -1,0 +1,53 @@
+"""CPU-side checks of the C ABI: the HIP library loads and exports every entry point
+include/nlse.h declares, and the binding's struct matches the header's layout.
+No GPU work is launched here."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(nlse_\w+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1109_1027_amd as P
+    lib = P.load()
+    names = declared()
+    assert {"nlse_create", "nlse_set_field", "nlse_step", "nlse_get_field", "nlse_mass"} <= names
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
+def test_params_struct_layout():
+    """nlse_params: int32 ndim; int64 n[3]; double h, a, s; const double *V; int32 bc, prec,
+    allow_unstable; void *stream  ->  offsets as a C compiler lays them out."""
+    from paper_1109_1027_amd.nlse import Params
+    assert Params.n.offset == 8
+    assert Params.h.offset == 32
+    assert Params.V.offset == 56
+    assert Params.bc.offset == 64
+    assert Params.stream.offset == 80
+    assert ctypes.sizeof(Params) == 88
+
+
+def test_no_gpu_gives_error_not_crash():
+    """Without a GPU the library reports an error code instead of faulting (and never falls back)."""
+    import torch
+    if torch.cuda.is_available():
+        return
+    import paper_1109_1027_amd as P
+    try:
+        P.Solver(2, 8, 0.1, 1.0, 1.0, stream=None)
+    except P.NLSEError as e:
+        assert e.code in (-4, -5)
+    else:
+        raise AssertionError("expected an error without a GPU")

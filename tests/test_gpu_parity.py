@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (relative L2 over all nodes after the whole run):
+  FP64 <= 1e-12, FP32 and mixed <= 1e-4  (rounding-order differences only; the
+  oracle has no FMA, the GPU contracts).
+Sizes span several tiles with ragged tails in every axis (2D tiles: 64 columns x 8
+rows; 3D tiles: 64 x 4 columns x 32 planes).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import nlse_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-4, "mixed": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1109_1027_amd as P
+    P.load()
+    return P
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_both(gpu, orc, spec, prec, nsteps, dt=None, frac=0.5):
+    P = orc.Problem.from_spec(spec)
+    if dt is None:
+        dt = frac * P.max_dt(spec.psi0)
+    say(f"[case] {spec.name} dim={spec.dim} n={spec.grid.n} prec={prec} steps={nsteps} dt={dt:.6g}")
+    s = gpu.Solver.from_spec(spec, prec=prec)
+    s.set_field(spec.psi0)
+    s.step(nsteps, dt)
+    g = s.get_field()
+    ref = P.rk4(spec.psi0, nsteps, dt)
+    return g, ref, s, P
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a, np.complex128) - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def with_random_boundary(spec, seed=5, amp=0.3):
+    """Same problem with non-zero (random, fixed) Dirichlet boundary values."""
+    rng = np.random.default_rng(seed)
+    psi = spec.psi0.copy()
+    m = spec.grid.boundary_mask()
+    psi[m] = amp * (rng.standard_normal(m.sum()) + 1j * rng.standard_normal(m.sum()))
+    return I.ProblemSpec(spec.name + "_bnd", spec.grid, spec.a, spec.s, spec.V, psi, spec.bc)
+
+
+# ------------------------------------------------------------------- 2D --
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+@pytest.mark.parametrize("n", [5, 70, 150])
+def test_2d_gp_parity(gpu, orc, prec, n):
+    sp = I.config_gp2d(n=n)
+    g, ref, s, P = run_both(gpu, orc, sp, prec, 30)
+    assert rel(g, ref) <= TOL[prec], rel(g, ref)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_2d_nonzero_boundary_parity(gpu, orc, prec):
+    """Non-zero Dirichlet values exercise the boundary-face closure (Eq. dbc_lap)."""
+    sp = with_random_boundary(I.config_gp2d(n=131))
+    g, ref, s, P = run_both(gpu, orc, sp, prec, 25)
+    assert rel(g, ref) <= TOL[prec]
+    m = sp.grid.boundary_mask()
+    got = g.astype(np.complex128)[m]
+    want = sp.psi0[m].astype(np.complex64 if prec == "f32" else np.complex128)
+    assert np.array_equal(got, want.astype(np.complex128)), "Dirichlet values must stay fixed"
+
+
+def test_2d_paper_fig2_h_quarter(gpu, orc):
+    """Fig. 2 workload (linear Gaussian, V = r^2) at h = 1/4: the GPU reproduces the paper's digits."""
+    import json, os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_fig2_gaussian_2d.json")))
+    sp = I.paper_fig2(0.25)
+    c = sp.grid.coords()
+    s = gpu.Solver.from_spec(sp, prec="f64")
+    s.set_field(sp.psi0)
+    k = sp.t_end / sp.steps
+    er, ei = [], []
+    for j in range(1, 101):
+        s.step(sp.steps // 100, k)
+        g = s.get_field()
+        r, i = orc.rms_parts(g, I.gaussian_ho(c, j * (sp.steps // 100) * k))
+        er.append(r)
+        ei.append(i)
+    assert float(f"{np.mean(er):.5g}") == gold["shoc_error_real"][2]
+    assert float(f"{np.mean(ei):.5g}") == gold["shoc_error_imag"][2]
+
+
+def test_2d_full_size_two_steps(gpu, orc):
+    """The benchmark's workload (2049^2 nodes) in the benchmark's launch configuration."""
+    sp = I.config_gp2d(n=2048)
+    for prec in ("f64", "f32"):
+        g, ref, s, P = run_both(gpu, orc, sp, prec, 2)
+        assert rel(g, ref) <= TOL[prec], (prec, rel(g, ref))
+
+
+# ------------------------------------------------------------------- 1D --
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+def test_1d_soliton_full_run(gpu, orc, prec):
+    """Config 1: bright soliton, n = 1024, t = 10 (3955 steps): oracle parity and exact-solution error."""
+    sp = I.config_soliton_1d(1024)
+    P = orc.Problem.from_spec(sp)
+    nsteps, dt = orc.steps_for(10.0, P.max_dt(sp.psi0))
+    assert nsteps == 3955
+    g, ref, s, _ = run_both(gpu, orc, sp, prec, nsteps, dt)
+    assert rel(g, ref) <= TOL[prec]
+    (x,) = sp.grid.coords()
+    err = rel(g, I.bright_soliton(x, 10.0, 1.0, 1.0, 1.0, 0.5))
+    assert err == pytest.approx(1.31e-4, rel=0.02)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_1d_msd_dark_soliton(gpu, orc, prec):
+    sp = I.paper_fig1(0.25)
+    g, ref, s, P = run_both(gpu, orc, sp, prec, 2000, dt=0.0005)
+    assert rel(g, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("n", [2, 3, 1023, 5119])
+def test_1d_sizes(gpu, orc, n):
+    g = I.grid(1, n, -10, 10)
+    (x,) = g.coords()
+    psi = I.bright_soliton(x, 0.0, 1.0, 1.0, 1.2, 0.3)
+    psi[0] = psi[-1] = 0
+    sp = I.ProblemSpec("sizes1d", g, 1.0, 1.0, 0.05 * x * x, psi, "dirichlet")
+    gg, ref, s, P = run_both(gpu, orc, sp, "f64", 40)
+    assert rel(gg, ref) <= 1e-12
+
+
+# ------------------------------------------------------------------- 3D --
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+def test_3d_gp_parity(gpu, orc, prec):
+    sp = I.config_gp3d(n=70)
+    g, ref, s, P = run_both(gpu, orc, sp, prec, 8)
+    assert rel(g, ref) <= TOL[prec], rel(g, ref)
+
+
+def test_3d_nonzero_boundary_parity(gpu, orc):
+    sp = with_random_boundary(I.config_gp3d(n=37))
+    g, ref, s, P = run_both(gpu, orc, sp, "f64", 6)
+    assert rel(g, ref) <= 1e-12
+
+
+def test_3d_small(gpu, orc):
+    sp = I.config_gp3d(n=4)
+    g, ref, s, P = run_both(gpu, orc, sp, "f64", 3)
+    assert rel(g, ref) <= 1e-12
+
+
+# ---------------------------------------------------------- diagnostics --
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+def test_mass_energy_maxdt(gpu, orc, prec):
+    for sp in (I.config_gp2d(n=100), I.config_gp3d(n=30), I.config_soliton_1d(512), I.paper_fig1(0.5)):
+        P = orc.Problem.from_spec(sp)
+        s = gpu.Solver.from_spec(sp, prec=prec)
+        s.set_field(sp.psi0)
+        psi = sp.psi0.astype(np.complex64).astype(np.complex128) if prec == "f32" else sp.psi0
+        tol = 1e-12 if prec != "f32" else 1e-12
+        assert s.mass() == pytest.approx(P.mass(psi), rel=tol)
+        assert s.energy() == pytest.approx(P.energy(psi), rel=1e-10 if prec == "f64" else 1e-5, abs=1e-9)
+        assert s.max_dt() == pytest.approx(P.max_dt(psi), rel=1e-12 if prec == "f64" else 1e-6)
+
+
+def test_mass_deterministic_and_conserved(gpu, orc):
+    sp = I.config_soliton_1d(1024)
+    s = gpu.Solver.from_spec(sp)
+    s.set_field(sp.psi0)
+    m0 = s.mass()
+    assert s.mass() == m0
+    s.step(3955, 10.0 / 3955)
+    assert abs(s.mass() - m0) / m0 < 1e-12
+
+
+# ------------------------------------------------------- ABI behaviour --
+
+def test_dt_rejected_above_bound(gpu):
+    sp = I.config_gp2d(n=64)
+    s = gpu.Solver.from_spec(sp)
+    s.set_field(sp.psi0)
+    k = s.max_dt()
+    with pytest.raises(gpu.NLSEError) as e:
+        s.step(1, 1.01 * k)
+    assert e.value.code == -2
+    s.step(1, 0.99 * k)
+    with pytest.raises(gpu.NLSEError):
+        s.step(1, -1.0)
+
+
+def test_unstable_run_reports_nonfinite(gpu):
+    sp = I.config_gp2d(n=64)
+    s = gpu.Solver.from_spec(sp, allow_unstable=True)
+    s.set_field(sp.psi0)
+    k = s.max_dt()
+    s.step(3000, 3.0 * k)
+    with pytest.raises(gpu.NLSEError) as e:
+        s.mass()
+    assert e.value.code == -3
+
+
+def test_invalid_params(gpu):
+    with pytest.raises(gpu.NLSEError) as e:
+        gpu.Solver(2, 10, 0.1, -1.0, 1.0)
+    assert e.value.code == -1
+    with pytest.raises(gpu.NLSEError) as e:
+        gpu.Solver(2, 10, 0.1, 1.0, 1.0, bc="msd")
+    assert e.value.code == -6
+
+
+def test_checkpoint_resume_bitwise(gpu):
+    sp = I.config_gp2d(n=90)
+    s = gpu.Solver.from_spec(sp)
+    s.set_field(sp.psi0)
+    k = 0.5 * s.max_dt()
+    s.step(20, k)
+    full = s.get_field()
+    a = gpu.Solver.from_spec(sp)
+    a.set_field(sp.psi0)
+    a.step(8, k)
+    mid = a.get_field()
+    b = gpu.Solver.from_spec(sp, allow_unstable=True)
+    b.set_field(mid)
+    b.step(12, k)
+    assert np.array_equal(b.get_field(), full)
+
+
+def test_device_pointer_roundtrip(gpu):
+    import torch
+    sp = I.config_gp2d(n=40)
+    s = gpu.Solver.from_spec(sp, prec="f32")
+    t = torch.from_numpy(sp.psi0.astype(np.complex64)).cuda()
+    s.set_field(t)
+    out = torch.empty_like(t)
+    s.get_field(out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), sp.psi0.astype(np.complex64))
