@@ -51,10 +51,12 @@ def measured_traffic(prec, launches_ratio=1.0):
 
 
 def time_solver(P, spec, prec, steps, warmup):
+    """Time `steps` RK4 steps after `warmup` untimed ones; HIP events on the solver's stream."""
     import torch
     s = P.Solver.from_spec(spec, prec=prec)
     s.set_field(spec.psi0)
     dt = 0.5 * s.max_dt()
+    variant = s.autotune(reps=5)       # tile shape chosen by the library's autotuner (untimed)
     s.step(warmup, dt)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -70,7 +72,7 @@ def time_solver(P, spec, prec, steps, warmup):
     mass = s.mass()
     launches = s.launches_per_step() * steps
     s.close()
-    return ms, wall, launches, dt, mass
+    return ms, wall, launches, dt, mass, variant
 
 
 def copy_ceiling_gbs():
@@ -107,6 +109,30 @@ def cpu_baseline(spec, budget_s=12.0):
             "sample": f"{steps} RK4 steps of the FP64 oracle on the full 2049^2 grid ({el:.1f} s)"}
 
 
+def bench_3d(P, I, args):
+    """The 3D Gross-Pitaevskii workload (HBM-resident working set of ~5 GB at 513^3)."""
+    spec = I.config_gp3d(n=args.n3d)
+    npts = spec.interior_points
+    res = {"workload": f"3D Gross-Pitaevskii 2SHOC-RK4, {args.n3d + 1}^3 nodes, a=0.5 s=-1 omega=0.1 on "
+                       "[-24,24]^3, Dirichlet 0, Thomas-Fermi cloud x vortex-ring phase",
+           "interior_points": npts, "steps": args.steps3d}
+    for prec in args.precs3d.split(","):
+        ms, wall, launches, dt, mass, variant = time_solver(P, spec, prec, args.steps3d, 5)
+        gpts = npts * args.steps3d / (ms * 1e-3) / 1e9
+        per_launch_bytes = BYTES_PER_POINT_STEP[prec] * npts / 4
+        achieved = per_launch_bytes / (ms * 1e-3 / launches) / 1e9
+        res[prec] = {"value": gpts, "unit": "Gpt·steps/s", "ms_per_step": ms / args.steps3d, "dt": dt,
+                     "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                                  "kernel": "nlse::stage3d_kernel",
+                                  "algorithmic_bytes_per_launch": per_launch_bytes,
+                                  "avg_launch_us": ms * 1e3 / launches, "tile_variant": variant}}
+        print(f"[bench] 3D {prec}: {gpts:.2f} Gpt*steps/s, {ms / args.steps3d:.3f} ms/step, "
+              f"{achieved:.0f} GB/s algorithmic ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)",
+              file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +141,9 @@ def main():
     ap.add_argument("--n", type=int, default=2048, help="intervals per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precs", default="f64,f32,mixed")
+    ap.add_argument("--n3d", type=int, default=512, help="intervals per axis of the 3D workload (0: skip)")
+    ap.add_argument("--precs3d", default="f32,mixed")
+    ap.add_argument("--steps3d", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -131,7 +160,7 @@ def main():
     precs = args.precs.split(",")
     res = {}
     for prec in precs:
-        ms, wall, launches, dt, mass = time_solver(P, spec, prec, args.steps, args.warmup)
+        ms, wall, launches, dt, mass, variant = time_solver(P, spec, prec, args.steps, args.warmup)
         gpts = npts * args.steps / (ms * 1e-3) / 1e9
         per_launch_bytes = BYTES_PER_POINT_STEP[prec] * npts / 4
         avg_launch_s = ms * 1e-3 / launches
@@ -142,7 +171,7 @@ def main():
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
                          "kernel": "nlse::stage2d_kernel", "algorithmic_bytes_per_launch": per_launch_bytes,
-                         "avg_launch_us": avg_launch_s * 1e6},
+                         "avg_launch_us": avg_launch_s * 1e6, "tile_variant": variant},
         }
         print(f"[bench] {prec}: {gpts:.2f} Gpt*steps/s, {ms / args.steps:.4f} ms/step, "
               f"{achieved:.0f} GB/s algorithmic ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)",
@@ -167,6 +196,8 @@ def main():
     except Exception as e:  # context only
         out["copy_ceiling_gbs"] = None
         print(f"[bench] copy ceiling failed: {e}", file=sys.stderr)
+    if args.n3d > 0:
+        out["gp3d"] = bench_3d(P, I, args)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec)

@@ -132,6 +132,22 @@ const char *nlse_last_error(void);
  * report 0).  For throughput accounting. */
 int nlse_launches_per_step(const nlse_ctx *c);
 
+/* Tile-shape variants of the 2D / 3D stage kernels (2D: 64 columns x 8, 4 or 16 rows per
+ * wave; 3D: 64 x 4 or 64 x 8 columns marching 16, 32 or 64 planes).  Every variant
+ * computes bit-identical fields; they differ only in speed.  1D contexts have one. */
+int nlse_variant_count(const nlse_ctx *c);
+int nlse_set_variant(nlse_ctx *c, int variant);   /* NLSE_E_INVAL if out of range */
+int nlse_get_variant(const nlse_ctx *c);
+
+/* Autotuner: times `reps` stage launches of every variant on this context's own
+ * arrays (twice, keeping the fastest), selects the fastest and caches the choice for
+ * the process under (ndim, precision, n).  Later calls reuse the cached choice unless
+ * force != 0.  Needs a field (nlse_set_field); leaves the integration state unchanged
+ * (it only writes K_tot and a stage field that the next step overwrites before
+ * reading).  Waits for the stream.  The chosen variant is returned in *chosen
+ * (may be NULL). */
+int nlse_autotune(nlse_ctx *c, int reps, int force, int *chosen);
+
 #ifdef __cplusplus
 }
 #endif

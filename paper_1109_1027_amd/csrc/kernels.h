@@ -24,12 +24,15 @@ struct StageArgs {
     Layout L;
     Coeffs c;
     int stage;
+    int variant;        // tile-shape variant (see stage2d_variants / stage3d_variants)
 };
 
 // 2D fused stage kernel: per-axis 2SHOC, one 64-column x RW-row tile per wave.
 hipError_t launch_stage2d(Prec prec, const StageArgs &a, hipStream_t st);
+int stage2d_variants();
 // 3D fused stage kernel (2.5D: x-y tile in LDS, march along z).
 hipError_t launch_stage3d(Prec prec, const StageArgs &a, hipStream_t st);
+int stage3d_variants();
 
 // 1D persistent solver: one workgroup holds the whole field on chip and runs
 // nsteps RK4 steps in one launch.

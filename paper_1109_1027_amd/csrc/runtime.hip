@@ -13,7 +13,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.h"
@@ -55,6 +58,7 @@ struct nlse_ctx {
     hipStream_t stream = nullptr;
     double kmax = 0.0;
     bool have_field = false;
+    int variant = 0;            // tile-shape variant of the stage kernels
     std::vector<double> Vhost; // for host-side MSD closure (1D)
 };
 
@@ -89,9 +93,115 @@ static void free_ctx(nlse_ctx *c)
     delete c;
 }
 
+// Autotuner results shared by every context of the same shape in the process.
+using TuneKey = std::tuple<int, int, int64_t, int64_t, int64_t>;   // dim, precision, nx, ny, nz
+static std::map<TuneKey, int> g_tuned;
+static std::mutex g_tuned_mu;
+
+static TuneKey tune_key(const nlse_ctx *c) { return TuneKey(c->p.ndim, (int)c->prec, c->L.nx, c->L.ny, c->L.nz); }
+
+static int variant_count(const nlse_ctx *c)
+{
+    return c->p.ndim == 2 ? stage2d_variants() : c->p.ndim == 3 ? stage3d_variants() : 1;
+}
+
+static hipError_t launch_stage(nlse_ctx *c, int stage, double dt, int variant)
+{
+    const double ck[4] = {dt / 2.0, dt / 2.0, dt, dt / 6.0};
+    void *ins[4] = {c->psi, c->A, c->B, c->A};
+    void *outs[4] = {c->A, c->B, c->A, nullptr};
+    StageArgs a;
+    a.in = ins[stage - 1];
+    a.out = outs[stage - 1];
+    a.psin = c->psi;
+    a.K = c->K;
+    a.V = c->V;
+    for (int d = 0; d < 3; ++d) a.DB[d] = c->DB[d];
+    a.L = c->L;
+    a.c = base_coeffs(c->p);
+    a.c.ck = ck[stage - 1];
+    a.stage = stage;
+    a.variant = variant;
+    return c->p.ndim == 2 ? launch_stage2d(c->prec, a, c->stream) : launch_stage3d(c->prec, a, c->stream);
+}
+
 extern "C" {
 
 const char *nlse_last_error(void) { return g_err.c_str(); }
+
+int nlse_variant_count(const nlse_ctx *c)
+{
+    if (!c) return fail(NLSE_E_INVAL, "NULL context");
+    return variant_count(c);
+}
+
+int nlse_set_variant(nlse_ctx *c, int variant)
+{
+    if (!c) return fail(NLSE_E_INVAL, "NULL context");
+    if (variant < 0 || variant >= variant_count(c)) return fail(NLSE_E_INVAL, "variant out of range");
+    c->variant = variant;
+    return NLSE_OK;
+}
+
+int nlse_get_variant(const nlse_ctx *c)
+{
+    if (!c) return fail(NLSE_E_INVAL, "NULL context");
+    return c->variant;
+}
+
+int nlse_autotune(nlse_ctx *c, int reps, int force, int *chosen)
+{
+    if (!c) return fail(NLSE_E_INVAL, "NULL context");
+    if (!c->have_field) return fail(NLSE_E_INVAL, "no field set");
+    if (reps < 1) reps = 1;
+    const int nv = variant_count(c);
+    if (nv > 1) {
+        {
+            std::lock_guard<std::mutex> g(g_tuned_mu);
+            auto it = g_tuned.find(tune_key(c));
+            if (!force && it != g_tuned.end()) {
+                c->variant = it->second;
+                if (chosen) *chosen = c->variant;
+                return NLSE_OK;
+            }
+        }
+        // Time stage-2 launches (A -> B, K updated in place).  They only write K and the
+        // interior of B, which the next RK4 step overwrites before reading, so tuning
+        // leaves the state of the integration untouched.
+        const double dt = 0.5 * c->kmax;
+        hipEvent_t e0, e1;
+        HIPTRY(hipEventCreate(&e0));
+        HIPTRY(hipEventCreate(&e1));
+        float best = 1e30f;
+        int bestv = 0;
+        for (int round = 0; round < 2; ++round) {
+            for (int v = 0; v < nv; ++v) {
+                hipError_t e = launch_stage(c, 2, dt, v);   // warm
+                if (e != hipSuccess) return hipfail(e, "autotune launch");
+                HIPTRY(hipEventRecord(e0, c->stream));
+                for (int r = 0; r < reps; ++r) {
+                    e = launch_stage(c, 2, dt, v);
+                    if (e != hipSuccess) return hipfail(e, "autotune launch");
+                }
+                HIPTRY(hipEventRecord(e1, c->stream));
+                HIPTRY(hipEventSynchronize(e1));
+                float ms;
+                HIPTRY(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    bestv = v;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c->variant = bestv;
+        std::lock_guard<std::mutex> g(g_tuned_mu);
+        g_tuned[tune_key(c)] = bestv;
+    }
+    if (chosen) *chosen = c->variant;
+    return NLSE_OK;
+}
 
 int nlse_create(nlse_ctx **out, const nlse_params *p)
 {
@@ -339,24 +449,9 @@ int nlse_step(nlse_ctx *c, int64_t nsteps, double dt)
         HIPTRY(launch_solve1d(c->prec, a, c->stream));
         return NLSE_OK;
     }
-    const double ck[4] = {dt / 2.0, dt / 2.0, dt, dt / 6.0};
-    void *ins[4] = {c->psi, c->A, c->B, c->A};
-    void *outs[4] = {c->A, c->B, c->A, nullptr};
     for (int64_t step = 0; step < nsteps; ++step) {
-        for (int st = 0; st < 4; ++st) {
-            StageArgs a;
-            a.in = ins[st];
-            a.out = outs[st];
-            a.psin = c->psi;
-            a.K = c->K;
-            a.V = c->V;
-            for (int d = 0; d < 3; ++d) a.DB[d] = c->DB[d];
-            a.L = c->L;
-            a.c = co;
-            a.c.ck = ck[st];
-            a.stage = st + 1;
-            hipError_t e = c->p.ndim == 2 ? launch_stage2d(c->prec, a, c->stream)
-                                          : launch_stage3d(c->prec, a, c->stream);
+        for (int st = 1; st <= 4; ++st) {
+            hipError_t e = launch_stage(c, st, dt, c->variant);
             if (e != hipSuccess) return hipfail(e, "stage kernel launch");
         }
     }

@@ -17,7 +17,8 @@
 // once per field (launch_boundary_d) and read here only by boundary tiles.
 //
 // Tiling.  A wave owns 64 consecutive interior columns (aligned, one row segment
-// = one coalesced access) and RW rows.  It loads RW + 4 rows of its columns
+// = one coalesced access) and RW rows (RW = 4, 8 or 16: the tile variants the
+// autotuner chooses from; every variant computes bit-identical results).  It loads RW + 4 rows of its columns
 // (2-row halo for D^y at the tile's first/last rows), and one extra masked load
 // brings the 2-column halo on each side for the RW rows.  Blocks of 4 waves
 // take 4 consecutive tiles along x; blocks are remapped so that each XCD owns a
@@ -34,7 +35,8 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs A, int64_t tiles
 {
     static_assert(RW <= 16, "halo load covers at most 16 rows");
     constexpr int W = 64, NW = 4, SP = W + 4;
-    __shared__ C<R> lds[NW][RW][SP];
+    __shared__ C<R> lds[NW][RW][SP];      // Psi rows, columns x0-2 .. x0+65
+    __shared__ C<R> ldx[NW][RW][W + 2];   // D^x rows, columns x0-1 .. x0+64
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const Layout L = A.L;
@@ -103,25 +105,21 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs A, int64_t tiles
         dx[r] = cscale<R>(ih2, cadd<R>(csub<R>(rr, cscale<R>(two, c)), l));
         if (xnode && x == L.nx && y0 + r <= L.ny) dx[r] = DBx[(L.ny + 1) + y0 + r];   // face x = nx
     }
-    C<R> hdx = czero<R>();
-    int hpos = 0;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) ldx[wv][r][lane + 1] = dx[r];
     if (valid && lane < 2 * RW) {
         const int r = lane >> 1, side = lane & 1;
         const int c = side ? W + 2 : 1;               // LDS column of x0+64 or x0-1
         const C<R> l = lds[wv][r][c - 1], m = lds[wv][r][c], rr = lds[wv][r][c + 1];
-        hdx = cscale<R>(ih2, cadd<R>(csub<R>(rr, cscale<R>(two, m)), l));
+        C<R> hdx = cscale<R>(ih2, cadd<R>(csub<R>(rr, cscale<R>(two, m)), l));
         const int64_t hx = side ? x0 + W : x0 - 1;
         const int64_t y = y0 + r;
         if (y <= L.ny) {
             if (hx == 0) hdx = DBx[y];
             else if (hx == L.nx) hdx = DBx[(L.ny + 1) + y];
         }
-        hpos = side ? W + 1 : 0;
+        ldx[wv][r][side ? W + 1 : 0] = hdx;
     }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < RW; ++r) lds[wv][r][lane + 1] = dx[r];
-    if (valid && lane < 2 * RW) lds[wv][lane >> 1][hpos] = hdx;
 
     // ---- step 1 along y: registers
     C<R> dy[RW + 2];
@@ -139,7 +137,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs A, int64_t tiles
     for (int r = 0; r < RW; ++r) {
         const int64_t y = y0 + r;
         if (!(xnode && x < L.nx && y < L.ny)) continue;
-        const C<R> dxl = lds[wv][r][lane], dxr = lds[wv][r][lane + 2];
+        const C<R> dxl = ldx[wv][r][lane], dxr = ldx[wv][r][lane + 2];
         const C<R> lap = csub<R>(cscale<R>(c76, cadd<R>(dx[r], dy[r + 1])),
                                  cscale<R>(c112, cadd<R>(cadd<R>(dxr, dxl), cadd<R>(dy[r + 2], dy[r]))));
         const C<R> u = col[r + 2];
@@ -175,15 +173,27 @@ static hipError_t launch_rw(const StageArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
+template <typename IN, typename R, typename M>
+static hipError_t launch2v(const StageArgs &a, hipStream_t st)
+{
+    switch (a.variant) {
+    case 0: return launch_rw<IN, R, M, 8>(a, st);
+    case 1: return launch_rw<IN, R, M, 4>(a, st);
+    case 2: return launch_rw<IN, R, M, 16>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int stage2d_variants() { return 3; }
+
 hipError_t launch_stage2d(Prec prec, const StageArgs &a, hipStream_t st)
 {
-    constexpr int RW = 8;
     switch (prec) {
-    case P_F64: return launch_rw<double, double, double, RW>(a, st);
-    case P_F32: return launch_rw<float, float, float, RW>(a, st);
+    case P_F64: return launch2v<double, double, double>(a, st);
+    case P_F32: return launch2v<float, float, float>(a, st);
     default:
-        if (a.stage == 1) return launch_rw<double, float, double, RW>(a, st);
-        return launch_rw<float, float, double, RW>(a, st);
+        if (a.stage == 1) return launch2v<double, float, double>(a, st);
+        return launch2v<float, float, double>(a, st);
     }
 }
 

@@ -10,6 +10,11 @@
 // Psi (with a 2-node halo in x and y) and the in-plane D^x, D^y (with a 1-node
 // halo) go through LDS.  No D value is ever written to global memory.
 //
+// Software pipelining: everything plane z+1 needs from global memory (Psi at
+// z+3, the plane's x/y halo, and the update operands Psi^n, K_tot, V) is loaded
+// while plane z is computed, so a plane never waits a full memory round trip.
+// Barriers only order LDS (they wait on LDS counters, not on loads in flight).
+//
 // Face closure values D^a_b (boundary-face nodes) are the Dirichlet constants of
 // launch_boundary_d; see stage2d.hip for why the per-axis and single-storage
 // forms then coincide.
@@ -66,41 +71,52 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int64_t 
         if (zz == L.nz) return DBz[fz + y * (L.nx + 1) + x];
         return d2(m, c, p);
     };
+    // halo of plane zz: x-halo (4 columns x TYB rows), y-halo (4 rows x 64 columns)
+    auto ld_hx = [&](int64_t zz) -> C<R> {
+        if (t >= 4 * TYB) return czero<R>();
+        const int r = t >> 2, k = t & 3;
+        return ld(x0 + (k == 0 ? -2 : k == 1 ? -1 : k == 2 ? W : W + 1), y0 + r, zz);
+    };
+    auto ld_hy = [&](int64_t zz) -> C<R> {
+        if (t >= 4 * W) return czero<R>();
+        const int k = t >> 6, c = t & 63;
+        return ld(x0 + c, y0 + (k == 0 ? -2 : k == 1 ? -1 : k == 2 ? TYB : TYB + 1), zz);
+    };
+    struct Ops { C<M> pn; C<R> kt; R vv; };
+    auto ld_ops = [&](int64_t zz) -> Ops {
+        Ops o;
+        o.pn = mk<M>(M(0), M(0));
+        o.kt = czero<R>();
+        o.vv = R(0);
+        if (upd_col && zz < L.nz) {
+            const int64_t p = L.idx(x, y, zz);
+            if (stage >= 2 || !in_is_r) o.pn = psin[p];
+            if (stage >= 2) o.kt = K[p];
+            if (V) o.vv = V[p];
+        }
+        return o;
+    };
 
-    // register queue: q[k] = Psi(z - 2 + k) of the own column
+    // prologue: queue for the first plane, its halo and its update operands
     C<R> q[5];
-    q[0] = col_ok ? ld(x, y, z0 - 2) : czero<R>();
-    q[1] = col_ok ? ld(x, y, z0 - 1) : czero<R>();
-    q[2] = col_ok ? ld(x, y, z0) : czero<R>();
-    q[3] = col_ok ? ld(x, y, z0 + 1) : czero<R>();
+#pragma unroll
+    for (int k = 0; k < 5; ++k) q[k] = col_ok ? ld(x, y, z0 - 2 + k) : czero<R>();
+    C<R> hx = ld_hx(z0), hy = ld_hy(z0);
+    Ops ops = ld_ops(z0);
     C<R> dzm = dz_at(z0 - 1, q[0], q[1], q[2]);
     C<R> dz0 = dz_at(z0, q[1], q[2], q[3]);
 
     for (int zi = 0; zi < TZ; ++zi) {
         const int64_t z = z0 + zi;
         if (z >= L.nz) break;   // block-uniform
-        q[4] = col_ok ? ld(x, y, z + 2) : czero<R>();
-        // halo of plane z: x-halo (4 columns x TYB rows), y-halo (4 rows x 64 columns)
-        C<R> hx = czero<R>(), hy = czero<R>();
-        if (t < 4 * TYB) {
-            const int r = t >> 2, k = t & 3;
-            hx = ld(x0 + (k == 0 ? -2 : k == 1 ? -1 : k == 2 ? W : W + 1), y0 + r, z);
-        }
-        if (t < 4 * W) {
-            const int k = t >> 6, c = t & 63;
-            hy = ld(x0 + c, y0 + (k == 0 ? -2 : k == 1 ? -1 : k == 2 ? TYB : TYB + 1), z);
-        }
-        // update operands of plane z
-        const bool upd = upd_col && z < L.nz;
-        const int64_t p = L.idx(x, y, z);
-        C<M> pn = mk<M>(M(0), M(0));
-        C<R> kt = czero<R>();
-        R vv = R(0);
-        if (upd && (stage >= 2 || !in_is_r)) pn = psin[p];
-        if (upd && stage >= 2) kt = K[p];
-        if (upd && V) vv = V[p];
-        const C<R> dzp = dz_at(z + 1, q[2], q[3], q[4]);
+        // prefetch plane z+1
+        const bool more = (zi + 1 < TZ) && (z + 1 < L.nz);
+        const C<R> q5 = (more && col_ok) ? ld(x, y, z + 3) : czero<R>();
+        const C<R> nhx = more ? ld_hx(z + 1) : czero<R>();
+        const C<R> nhy = more ? ld_hy(z + 1) : czero<R>();
+        const Ops nops = more ? ld_ops(z + 1) : Ops{mk<M>(M(0), M(0)), czero<R>(), R(0)};
 
+        const C<R> dzp = dz_at(z + 1, q[2], q[3], q[4]);
         sp[ty + 2][tx + 2] = q[2];
         if (t < 4 * TYB) {
             const int r = t >> 2, k = t & 3;
@@ -116,59 +132,62 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int64_t 
         C<R> dy = d2(sp[ty + 1][tx + 2], sp[ty + 2][tx + 2], sp[ty + 3][tx + 2]);
         if (col_ok && x == L.nx) dx = DBx[fx + z * (L.ny + 1) + y];
         if (col_ok && y == L.ny) dy = DBy[fy + z * (L.nx + 1) + x];
-        C<R> hdx = czero<R>(), hdy = czero<R>();
+        sdx[ty][tx + 1] = dx;
+        sdy[ty + 1][tx] = dy;
         if (t < 2 * TYB) {
             const int r = t >> 1, side = t & 1;
             const int c = side ? W + 2 : 1;
-            hdx = d2(sp[r + 2][c - 1], sp[r + 2][c], sp[r + 2][c + 1]);
+            C<R> hdx = d2(sp[r + 2][c - 1], sp[r + 2][c], sp[r + 2][c + 1]);
             const int64_t hxx = side ? x0 + W : x0 - 1, yy = y0 + r;
             if (yy <= L.ny) {
                 if (hxx == 0) hdx = DBx[z * (L.ny + 1) + yy];
                 else if (hxx == L.nx) hdx = DBx[fx + z * (L.ny + 1) + yy];
             }
+            sdx[r][side ? W + 1 : 0] = hdx;
         }
         if (t < 2 * W) {
             const int side = t >> 6, c = t & 63;
             const int r = side ? TYB + 2 : 1;
-            hdy = d2(sp[r - 1][c + 2], sp[r][c + 2], sp[r + 1][c + 2]);
+            C<R> hdy = d2(sp[r - 1][c + 2], sp[r][c + 2], sp[r + 1][c + 2]);
             const int64_t yy = side ? y0 + TYB : y0 - 1, xx = x0 + c;
             if (xx <= L.nx) {
                 if (yy == 0) hdy = DBy[z * (L.nx + 1) + xx];
                 else if (yy == L.ny) hdy = DBy[fy + z * (L.nx + 1) + xx];
             }
+            sdy[side ? TYB + 1 : 0][c] = hdy;
         }
         __syncthreads();
-        sdx[ty][tx + 1] = dx;
-        sdy[ty + 1][tx] = dy;
-        if (t < 2 * TYB) sdx[t >> 1][(t & 1) ? W + 1 : 0] = hdx;
-        if (t < 2 * W) sdy[(t >> 6) ? TYB + 1 : 0][t & 63] = hdy;
-        __syncthreads();
-        if (upd) {
+        if (upd_col) {
+            const int64_t p = L.idx(x, y, z);
             const C<R> nb = cadd<R>(cadd<R>(cadd<R>(sdx[ty][tx + 2], sdx[ty][tx]), cadd<R>(sdy[ty + 2][tx], sdy[ty][tx])),
                                     cadd<R>(dzp, dzm));
             const C<R> lap = csub<R>(cscale<R>(c76, cadd<R>(cadd<R>(dx, dy), dz0)), cscale<R>(c112, nb));
             const C<R> u = q[2];
-            const R nl = s * (u.x * u.x + u.y * u.y) - vv;
+            const R nl = s * (u.x * u.x + u.y * u.y) - ops.vv;
             const C<R> zz = cadd<R>(cscale<R>(a, lap), cscale<R>(nl, u));
             const C<R> F = mk<R>(-zz.y, zz.x);
             if (stage == 1) {
-                const C<M> base = in_is_r ? cvt<M, R>(u) : pn;
+                const C<M> base = in_is_r ? cvt<M, R>(u) : ops.pn;
                 K[p] = F;
                 const C<R> inc = cscale<R>(ck, F);
                 out[p] = cvt<R, M>(mk<M>(base.x + (M)inc.x, base.y + (M)inc.y));
             } else if (stage <= 3) {
-                K[p] = cadd<R>(kt, cscale<R>(two, F));
+                K[p] = cadd<R>(ops.kt, cscale<R>(two, F));
                 const C<R> inc = cscale<R>(ck, F);
-                out[p] = cvt<R, M>(mk<M>(pn.x + (M)inc.x, pn.y + (M)inc.y));
+                out[p] = cvt<R, M>(mk<M>(ops.pn.x + (M)inc.x, ops.pn.y + (M)inc.y));
             } else {
-                const C<R> inc = cscale<R>(ck, cadd<R>(kt, F));
-                psin[p] = mk<M>(pn.x + (M)inc.x, pn.y + (M)inc.y);
+                const C<R> inc = cscale<R>(ck, cadd<R>(ops.kt, F));
+                psin[p] = mk<M>(ops.pn.x + (M)inc.x, ops.pn.y + (M)inc.y);
             }
         }
         q[0] = q[1];
         q[1] = q[2];
         q[2] = q[3];
         q[3] = q[4];
+        q[4] = q5;
+        hx = nhx;
+        hy = nhy;
+        ops = nops;
         dzm = dz0;
         dz0 = dzp;
     }
@@ -186,15 +205,28 @@ static hipError_t launch3(const StageArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
+template <typename IN, typename R, typename M>
+static hipError_t launch3v(const StageArgs &a, hipStream_t st)
+{
+    switch (a.variant) {
+    case 0: return launch3<IN, R, M, 4, 32>(a, st);
+    case 1: return launch3<IN, R, M, 4, 64>(a, st);
+    case 2: return launch3<IN, R, M, 8, 32>(a, st);
+    case 3: return launch3<IN, R, M, 4, 16>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int stage3d_variants() { return 4; }
+
 hipError_t launch_stage3d(Prec prec, const StageArgs &a, hipStream_t st)
 {
-    constexpr int TYB = 4, TZ = 32;
     switch (prec) {
-    case P_F64: return launch3<double, double, double, TYB, TZ>(a, st);
-    case P_F32: return launch3<float, float, float, TYB, TZ>(a, st);
+    case P_F64: return launch3v<double, double, double>(a, st);
+    case P_F32: return launch3v<float, float, float>(a, st);
     default:
-        if (a.stage == 1) return launch3<double, float, double, TYB, TZ>(a, st);
-        return launch3<float, float, double, TYB, TZ>(a, st);
+        if (a.stage == 1) return launch3v<double, float, double>(a, st);
+        return launch3v<float, float, double>(a, st);
     }
 }
 

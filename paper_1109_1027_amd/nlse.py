@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
 
 
 EXPORTS = ["nlse_create", "nlse_set_field", "nlse_step", "nlse_get_field", "nlse_mass", "nlse_energy",
-           "nlse_max_dt", "nlse_sync", "nlse_destroy", "nlse_last_error", "nlse_launches_per_step"]
+           "nlse_max_dt", "nlse_sync", "nlse_destroy", "nlse_last_error", "nlse_launches_per_step",
+           "nlse_variant_count", "nlse_set_variant", "nlse_get_variant", "nlse_autotune"]
 
 _lib = None
 
@@ -60,6 +61,10 @@ def load():
     L.nlse_destroy.restype = None
     L.nlse_last_error.restype = ctypes.c_char_p
     L.nlse_launches_per_step.argtypes = [vp]
+    L.nlse_variant_count.argtypes = [vp]
+    L.nlse_set_variant.argtypes = [vp, ctypes.c_int]
+    L.nlse_get_variant.argtypes = [vp]
+    L.nlse_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     for f in EXPORTS:
         if f not in ("nlse_destroy", "nlse_last_error"):
             getattr(L, f).restype = ctypes.c_int
@@ -183,6 +188,24 @@ class Solver:
 
     def launches_per_step(self):
         return load().nlse_launches_per_step(self._h)
+
+    # ---- tile variants and the autotuner
+    def variant_count(self):
+        return load().nlse_variant_count(self._h)
+
+    @property
+    def variant(self):
+        return load().nlse_get_variant(self._h)
+
+    @variant.setter
+    def variant(self, v):
+        _check(load().nlse_set_variant(self._h, int(v)))
+
+    def autotune(self, reps=5, force=False):
+        """Time every tile variant on this problem, keep the fastest; returns its index."""
+        ch = ctypes.c_int()
+        _check(load().nlse_autotune(self._h, int(reps), int(bool(force)), ctypes.byref(ch)))
+        return ch.value
 
 
 def _is_torch(x):

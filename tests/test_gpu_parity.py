@@ -251,3 +251,96 @@ def test_device_pointer_roundtrip(gpu):
     s.get_field(out)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), sp.psi0.astype(np.complex64))
+
+
+# ------------------------------------------------------- config 3 runs --
+
+@pytest.fixture(scope="module")
+def gp3d_128_ref(orc):
+    """Config 3's parity run: the same 3D problem at 128 intervals (129^3 nodes), 500 steps."""
+    sp = I.config_gp3d(n=128)
+    P = orc.Problem.from_spec(sp)
+    dt = 0.5 * P.max_dt(sp.psi0)
+    say("[case] oracle: 3D GP 129^3, 500 RK4 steps")
+    return sp, P, dt, P.rk4(sp.psi0, 500, dt)
+
+
+@pytest.mark.parametrize("prec", ["f32", "mixed"])
+def test_3d_config3_parity_run(gpu, gp3d_128_ref, prec):
+    sp, P, dt, ref = gp3d_128_ref
+    say(f"[case] 3D GP 129^3 {prec} 500 steps")
+    s = gpu.Solver.from_spec(sp, prec=prec)
+    s.set_field(sp.psi0)
+    s.step(500, dt)
+    g = s.get_field()
+    err = rel(g, ref)
+    say(f"[result] 3D 129^3 {prec}: rel L2 vs FP64 oracle = {err:.3e}")
+    assert err <= TOL[prec]
+    assert s.mass() == pytest.approx(P.mass(ref), rel=1e-5)
+
+
+def test_3d_full_size_sampled(gpu, orc):
+    """513^3 (config 3's full size) in the benchmark's launch configuration: one RK4 step on the
+    GPU, each sampled node checked against the oracle run on the node's dependency patch
+    (radius 10 > the 8 nodes one RK4 step reaches; patches clipped at the true boundary)."""
+    sp = I.config_gp3d(n=512)
+    n = sp.grid.n
+    P0 = orc.Problem.from_spec(sp)
+    dt = 0.5 * P0.max_dt(sp.psi0)
+    for prec in ("f32", "f64"):
+        say(f"[case] 3D GP 513^3 {prec} 1 step, sampled")
+        s = gpu.Solver.from_spec(sp, prec=prec)
+        s.set_field(sp.psi0)
+        s.autotune(reps=2)
+        s.step(1, dt)
+        g = s.get_field()
+        s.close()
+        rng = np.random.default_rng(11)
+        pts = [(1, 1, 1), (n - 1, n - 1, n - 1), (1, 256, 300), (64, 65, 33), (255, 256, 257), (511, 2, 128)]
+        pts += [tuple(int(v) for v in rng.integers(1, n, 3)) for _ in range(14)]
+        errs = []
+        for (z, y, x) in pts:
+            lo = [max(0, c - 10) for c in (z, y, x)]
+            hi = [min(n, c + 10) for c in (z, y, x)]
+            sl = tuple(slice(l, h + 1) for l, h in zip(lo, hi))
+            sub = sp.psi0[sl]
+            # patch edges that are not true boundaries are held fixed; they sit >= 10 nodes away
+            Pp = orc.Problem(3, (hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0]), sp.grid.h, sp.a, sp.s, sp.V[sl])
+            r = Pp.rk4(sub, 1, dt)[z - lo[0], y - lo[1], x - lo[2]]
+            errs.append(abs(complex(g[z, y, x]) - r) / max(abs(r), 1e-3))
+        say(f"[result] 3D 513^3 {prec}: max sampled rel err {max(errs):.3e}")
+        assert max(errs) <= (1e-12 if prec == "f64" else 1e-5)
+
+
+# ----------------------------------------------- tile variants, autotune --
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_variants_bitwise_identical(gpu, dim):
+    sp = I.config_gp2d(n=150) if dim == 2 else I.config_gp3d(n=70)
+    outs = []
+    s0 = gpu.Solver.from_spec(sp, prec="f32")
+    for v in range(s0.variant_count()):
+        s = gpu.Solver.from_spec(sp, prec="f32")
+        s.set_field(sp.psi0)
+        s.variant = v
+        say(f"[case] {dim}D variant {v}")
+        s.step(6, 0.5 * s.max_dt())
+        outs.append(s.get_field())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_autotune_keeps_state(gpu):
+    sp = I.config_gp2d(n=200)
+    a = gpu.Solver.from_spec(sp)
+    a.set_field(sp.psi0)
+    dt = 0.5 * a.max_dt()
+    a.step(3, dt)
+    v = a.autotune(reps=3, force=True)
+    assert 0 <= v < a.variant_count()
+    a.step(3, dt)
+    b = gpu.Solver.from_spec(sp)
+    b.set_field(sp.psi0)
+    b.variant = v
+    b.step(6, dt)
+    assert np.array_equal(a.get_field(), b.get_field())
