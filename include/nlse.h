@@ -148,6 +148,38 @@ int nlse_get_variant(const nlse_ctx *c);
  * (may be NULL). */
 int nlse_autotune(nlse_ctx *c, int reps, int force, int *chosen);
 
+/* ---------------------------------------------------------------- batches --
+ * Many independent 1D / 2D problems of uneven size advanced together by one
+ * persistent kernel launch (captured in a hipGraph).  Each instance has its own
+ * grid, coefficients, potential, boundary rule (MSD for 1D) and step dt; all
+ * share the precision and the stream of items[0].  Workgroups take instances
+ * longest-first from a device queue; a 1D instance (at most 8704 nodes in FP32 /
+ * mixed, 5120 in FP64) runs entirely on chip, a 2D instance is swept tile by tile
+ * by one workgroup.  Results are identical to advancing each instance alone. */
+typedef struct nlse_batch nlse_batch;
+
+/* items[i] as for nlse_create (ndim 1 or 2).  Allocates every instance. */
+int nlse_batch_create(nlse_batch **out, const nlse_params *items, int32_t count);
+int32_t nlse_batch_count(const nlse_batch *b);
+/* Field of instance i (as nlse_set_field; also evaluates that instance's bound). */
+int nlse_batch_set_field(nlse_batch *b, int32_t i, const void *psi, int on_device);
+int nlse_batch_get_field(nlse_batch *b, int32_t i, void *out, int on_device);
+/* Step size of instance i; NLSE_E_DT_UNSTABLE above its bound unless allow_unstable. */
+int nlse_batch_set_dt(nlse_batch *b, int32_t i, double dt);
+int nlse_batch_max_dt(nlse_batch *b, int32_t i, double *out);
+int nlse_batch_mass(nlse_batch *b, int32_t i, double *out);
+/* Every instance advances nsteps RK4 steps of its own dt: one graph launch on the
+ * stream (asynchronous).  NLSE_E_INVAL if an instance lacks a field or a dt. */
+int nlse_batch_step(nlse_batch *b, int64_t nsteps);
+int nlse_batch_sync(nlse_batch *b);
+/* Tile variants of the 2D instances (rows per wave: 8 or 4 in FP32 / mixed, 4 or 2
+ * in FP64) and the autotuner that times nsteps of each, restoring the state. */
+int nlse_batch_variant_count(const nlse_batch *b);
+int nlse_batch_set_variant(nlse_batch *b, int variant);
+int nlse_batch_get_variant(const nlse_batch *b);
+int nlse_batch_autotune(nlse_batch *b, int64_t nsteps, int force, int *chosen);
+void nlse_batch_destroy(nlse_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,14 +19,15 @@
 #include <tuple>
 #include <vector>
 
-#include "kernels.h"
-#include "../../include/nlse.h"
+#include "ctx.h"
 
 using namespace nlse;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace nlse {
 
 int fail(int code, const std::string &msg)
 {
@@ -39,30 +40,9 @@ int hipfail(hipError_t e, const char *what)
     return fail(NLSE_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIPTRY(call)                                         \
-    do {                                                     \
-        hipError_t e_ = (call);                              \
-        if (e_ != hipSuccess) return hipfail(e_, #call);     \
-    } while (0)
+}  // namespace nlse
 
-}  // namespace
-
-struct nlse_ctx {
-    nlse_params p;
-    Layout L;
-    Prec prec;
-    size_t esR, esM, rR;        // bytes: stage complex, master complex, stage real
-    void *psi = nullptr, *A = nullptr, *B = nullptr, *K = nullptr, *V = nullptr;
-    void *DB[3] = {nullptr, nullptr, nullptr};
-    double *red = nullptr;      // reduction partials (2 * reduce_partials()) + 2 result slots
-    hipStream_t stream = nullptr;
-    double kmax = 0.0;
-    bool have_field = false;
-    int variant = 0;            // tile-shape variant of the stage kernels
-    std::vector<double> Vhost; // for host-side MSD closure (1D)
-};
-
-static Coeffs base_coeffs(const nlse_params &p)
+Coeffs nlse::base_coeffs(const nlse_params &p)
 {
     Coeffs c;
     c.a = p.a;

@@ -23,142 +23,18 @@
 // brings the 2-column halo on each side for the RW rows.  Blocks of 4 waves
 // take 4 consecutive tiles along x; blocks are remapped so that each XCD owns a
 // contiguous band of tiles.
-#include "kernels.h"
+#include "tile2d.h"
 
 namespace nlse {
-
-template <typename T, typename U> struct same_t { static constexpr bool v = false; };
-template <typename T> struct same_t<T, T> { static constexpr bool v = true; };
 
 template <typename IN, typename R, typename M, int RW>
 __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs A, int64_t tiles_x, int64_t tiles_total)
 {
-    static_assert(RW <= 16, "halo load covers at most 16 rows");
-    constexpr int W = 64, NW = 4, SP = W + 4;
-    __shared__ C<R> lds[NW][RW][SP];      // Psi rows, columns x0-2 .. x0+65
-    __shared__ C<R> ldx[NW][RW][W + 2];   // D^x rows, columns x0-1 .. x0+64
-
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const Layout L = A.L;
-    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * NW + wv;
-    const bool valid = tile < tiles_total;
-    const int64_t tx = valid ? tile % tiles_x : 0, ty = valid ? tile / tiles_x : 0;
-    const int64_t x0 = 1 + W * tx, y0 = 1 + RW * ty;
-    const int64_t x = x0 + lane;
-    const bool xnode = valid && x <= L.nx;
-
-    const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
-    const R ck = (R)A.c.ck, two = (R)2;
-    const int stage = A.stage;
-    const C<IN> *in = (const C<IN> *)A.in;
-    const C<R> *DBx = (const C<R> *)A.DB[0];
-    const C<R> *DBy = (const C<R> *)A.DB[1];
-    const R *V = (const R *)A.V;
-    C<M> *psin = (C<M> *)A.psin;
-    C<R> *K = (C<R> *)A.K;
-    C<R> *out = (C<R> *)A.out;
-    constexpr bool in_is_r = same_t<IN, R>::v;
-
-    // ---- global loads: own column rows y0-2 .. y0+RW+1, then the update operands
-    C<R> col[RW + 4];
-#pragma unroll
-    for (int r = 0; r < RW + 4; ++r) {
-        const int64_t y = y0 - 2 + r;
-        col[r] = czero<R>();
-        if (xnode && y >= 0 && y <= L.ny) col[r] = cvt<R, IN>(in[L.idx(x, y, 0)]);
-    }
-    C<R> hv = czero<R>();
-    if (valid && lane < 4 * RW) {
-        const int r = lane >> 2, k = lane & 3;
-        const int64_t hx = x0 + (k == 0 ? -2 : k == 1 ? -1 : k == 2 ? W : W + 1);
-        const int64_t y = y0 + r;
-        if (hx >= 0 && hx <= L.nx && y <= L.ny) hv = cvt<R, IN>(in[L.idx(hx, y, 0)]);
-    }
-    C<M> pn[RW];
-    C<R> kt[RW];
-    R vv[RW];
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const int64_t y = y0 + r;
-        const bool upd = xnode && x < L.nx && y < L.ny;
-        const int64_t p = L.idx(x, y, 0);
-        pn[r] = mk<M>(M(0), M(0));
-        kt[r] = czero<R>();
-        vv[r] = R(0);
-        if (upd && (stage >= 2 || !in_is_r)) pn[r] = psin[p];
-        if (upd && stage >= 2) kt[r] = K[p];
-        if (upd && V) vv[r] = V[p];
-    }
-
-    // ---- step 1 along x: Psi row (+ halo) through LDS
-#pragma unroll
-    for (int r = 0; r < RW; ++r) lds[wv][r][lane + 2] = col[r + 2];
-    if (lane < 4 * RW) {
-        const int r = lane >> 2, k = lane & 3;
-        lds[wv][r][k == 0 ? 0 : k == 1 ? 1 : k == 2 ? W + 2 : W + 3] = hv;
-    }
-    __syncthreads();
-    C<R> dx[RW];
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const C<R> l = lds[wv][r][lane + 1], c = lds[wv][r][lane + 2], rr = lds[wv][r][lane + 3];
-        dx[r] = cscale<R>(ih2, cadd<R>(csub<R>(rr, cscale<R>(two, c)), l));
-        if (xnode && x == L.nx && y0 + r <= L.ny) dx[r] = DBx[(L.ny + 1) + y0 + r];   // face x = nx
-    }
-#pragma unroll
-    for (int r = 0; r < RW; ++r) ldx[wv][r][lane + 1] = dx[r];
-    if (valid && lane < 2 * RW) {
-        const int r = lane >> 1, side = lane & 1;
-        const int c = side ? W + 2 : 1;               // LDS column of x0+64 or x0-1
-        const C<R> l = lds[wv][r][c - 1], m = lds[wv][r][c], rr = lds[wv][r][c + 1];
-        C<R> hdx = cscale<R>(ih2, cadd<R>(csub<R>(rr, cscale<R>(two, m)), l));
-        const int64_t hx = side ? x0 + W : x0 - 1;
-        const int64_t y = y0 + r;
-        if (y <= L.ny) {
-            if (hx == 0) hdx = DBx[y];
-            else if (hx == L.nx) hdx = DBx[(L.ny + 1) + y];
-        }
-        ldx[wv][r][side ? W + 1 : 0] = hdx;
-    }
-
-    // ---- step 1 along y: registers
-    C<R> dy[RW + 2];
-#pragma unroll
-    for (int j = 0; j < RW + 2; ++j) {
-        const int64_t y = y0 - 1 + j;
-        dy[j] = cscale<R>(ih2, cadd<R>(csub<R>(col[j + 2], cscale<R>(two, col[j + 1])), col[j]));
-        if (xnode && y == 0) dy[j] = DBy[x];
-        if (xnode && y == L.ny) dy[j] = DBy[(L.nx + 1) + x];
-    }
-    __syncthreads();
-
-    // ---- step 2, F and the RK4 stage update
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const int64_t y = y0 + r;
-        if (!(xnode && x < L.nx && y < L.ny)) continue;
-        const C<R> dxl = ldx[wv][r][lane], dxr = ldx[wv][r][lane + 2];
-        const C<R> lap = csub<R>(cscale<R>(c76, cadd<R>(dx[r], dy[r + 1])),
-                                 cscale<R>(c112, cadd<R>(cadd<R>(dxr, dxl), cadd<R>(dy[r + 2], dy[r]))));
-        const C<R> u = col[r + 2];
-        const R nl = s * (u.x * u.x + u.y * u.y) - vv[r];
-        const C<R> z = cadd<R>(cscale<R>(a, lap), cscale<R>(nl, u));
-        const C<R> F = mk<R>(-z.y, z.x);
-        const int64_t p = L.idx(x, y, 0);
-        if (stage == 1) {
-            const C<M> base = in_is_r ? cvt<M, R>(u) : pn[r];
-            K[p] = F;
-            const C<R> inc = cscale<R>(ck, F);
-            out[p] = cvt<R, M>(mk<M>(base.x + (M)inc.x, base.y + (M)inc.y));
-        } else if (stage <= 3) {
-            K[p] = cadd<R>(kt[r], cscale<R>(two, F));
-            const C<R> inc = cscale<R>(ck, F);
-            out[p] = cvt<R, M>(mk<M>(pn[r].x + (M)inc.x, pn[r].y + (M)inc.y));
-        } else {
-            const C<R> inc = cscale<R>(ck, cadd<R>(kt[r], F));
-            psin[p] = mk<M>(pn[r].x + (M)inc.x, pn[r].y + (M)inc.y);
-        }
-    }
+    constexpr int NW = 4;
+    __shared__ C<R> lds[NW][RW][TILE_W + 4];      // Psi rows, columns x0-2 .. x0+65
+    __shared__ C<R> ldx[NW][RW][TILE_W + 2];      // D^x rows, columns x0-1 .. x0+64
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6);
+    stage2d_tile<IN, R, M, RW, NW>(A, tile, tiles_x, tiles_total, lds, ldx);
 }
 
 template <typename IN, typename R, typename M, int RW>

@@ -36,7 +36,11 @@ class Params(ctypes.Structure):
 
 EXPORTS = ["nlse_create", "nlse_set_field", "nlse_step", "nlse_get_field", "nlse_mass", "nlse_energy",
            "nlse_max_dt", "nlse_sync", "nlse_destroy", "nlse_last_error", "nlse_launches_per_step",
-           "nlse_variant_count", "nlse_set_variant", "nlse_get_variant", "nlse_autotune"]
+           "nlse_variant_count", "nlse_set_variant", "nlse_get_variant", "nlse_autotune",
+           "nlse_batch_create", "nlse_batch_count", "nlse_batch_set_field", "nlse_batch_get_field",
+           "nlse_batch_set_dt", "nlse_batch_max_dt", "nlse_batch_mass", "nlse_batch_step", "nlse_batch_sync",
+           "nlse_batch_variant_count", "nlse_batch_set_variant", "nlse_batch_get_variant",
+           "nlse_batch_autotune", "nlse_batch_destroy"]
 
 _lib = None
 
@@ -65,8 +69,24 @@ def load():
     L.nlse_set_variant.argtypes = [vp, ctypes.c_int]
     L.nlse_get_variant.argtypes = [vp]
     L.nlse_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    i32 = ctypes.c_int32
+    L.nlse_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), i32]
+    L.nlse_batch_count.argtypes = [vp]
+    L.nlse_batch_set_field.argtypes = [vp, i32, vp, ctypes.c_int]
+    L.nlse_batch_get_field.argtypes = [vp, i32, vp, ctypes.c_int]
+    L.nlse_batch_set_dt.argtypes = [vp, i32, dbl]
+    L.nlse_batch_max_dt.argtypes = [vp, i32, ctypes.POINTER(dbl)]
+    L.nlse_batch_mass.argtypes = [vp, i32, ctypes.POINTER(dbl)]
+    L.nlse_batch_step.argtypes = [vp, i64]
+    L.nlse_batch_sync.argtypes = [vp]
+    L.nlse_batch_variant_count.argtypes = [vp]
+    L.nlse_batch_set_variant.argtypes = [vp, ctypes.c_int]
+    L.nlse_batch_get_variant.argtypes = [vp]
+    L.nlse_batch_autotune.argtypes = [vp, i64, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.nlse_batch_destroy.argtypes = [vp]
+    L.nlse_batch_destroy.restype = None
     for f in EXPORTS:
-        if f not in ("nlse_destroy", "nlse_last_error"):
+        if f not in ("nlse_destroy", "nlse_last_error", "nlse_batch_destroy"):
             getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -210,3 +230,113 @@ class Solver:
 
 def _is_torch(x):
     return type(x).__module__.startswith("torch")
+
+
+def _params_from_spec(spec, prec, allow_unstable, stream):
+    """Params for one spec (nlse_inputs.ProblemSpec); returns (Params, V array kept alive)."""
+    g = spec.grid
+    p = Params()
+    p.ndim = g.dim
+    for i in range(3):
+        p.n[i] = g.n if i < g.dim else 0
+    p.h, p.a, p.s = g.h, float(spec.a), float(spec.s)
+    V = None
+    if spec.V is not None:
+        V = np.ascontiguousarray(spec.V, dtype=np.float64)
+        p.V = V.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.bc = BC[spec.bc]
+    p.prec = PREC[prec]
+    p.allow_unstable = int(bool(allow_unstable))
+    p.stream = stream
+    return p, V
+
+
+class Batch:
+    """Many independent 1D / 2D problems advanced by one persistent, graph-captured launch.
+
+    specs: sequence of nlse_inputs.ProblemSpec (1D or 2D).  set_fields() loads every
+    spec's psi0; set_dts(frac) gives each instance dt = frac * its own stability bound."""
+
+    def __init__(self, specs, prec="f32", allow_unstable=False, stream="current"):
+        L = load()
+        self.prec = prec
+        self.stream = _current_stream() if stream == "current" else stream
+        self.shapes = [tuple(v + 1 for v in (sp.grid.n,) * sp.grid.dim) for sp in specs]
+        self.dtype = np.complex64 if prec == "f32" else np.complex128
+        arr = (Params * len(specs))()
+        keep = []
+        for i, sp in enumerate(specs):
+            p, V = _params_from_spec(sp, prec, allow_unstable, self.stream)
+            arr[i] = p
+            keep.append(V)
+        h_ = ctypes.c_void_p()
+        _check(L.nlse_batch_create(ctypes.byref(h_), arr, len(specs)))
+        self._h = h_
+        self.count = len(specs)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().nlse_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_field(self, i, psi):
+        arr = np.ascontiguousarray(psi, dtype=self.dtype).reshape(self.shapes[i])
+        _check(load().nlse_batch_set_field(self._h, int(i), arr.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def get_field(self, i):
+        arr = np.empty(self.shapes[i], dtype=self.dtype)
+        _check(load().nlse_batch_get_field(self._h, int(i), arr.ctypes.data_as(ctypes.c_void_p), 0))
+        return arr
+
+    def set_dt(self, i, dt):
+        _check(load().nlse_batch_set_dt(self._h, int(i), float(dt)))
+
+    def max_dt(self, i):
+        v = ctypes.c_double()
+        _check(load().nlse_batch_max_dt(self._h, int(i), ctypes.byref(v)))
+        return v.value
+
+    def mass(self, i):
+        v = ctypes.c_double()
+        _check(load().nlse_batch_mass(self._h, int(i), ctypes.byref(v)))
+        return v.value
+
+    def set_fields(self, specs):
+        for i, sp in enumerate(specs):
+            self.set_field(i, sp.psi0)
+
+    def set_dts(self, frac=0.5):
+        dts = []
+        for i in range(self.count):
+            dt = frac * self.max_dt(i)
+            self.set_dt(i, dt)
+            dts.append(dt)
+        return dts
+
+    def step(self, nsteps):
+        _check(load().nlse_batch_step(self._h, int(nsteps)))
+
+    def sync(self):
+        _check(load().nlse_batch_sync(self._h))
+
+    @property
+    def variant(self):
+        return load().nlse_batch_get_variant(self._h)
+
+    @variant.setter
+    def variant(self, v):
+        _check(load().nlse_batch_set_variant(self._h, int(v)))
+
+    def variant_count(self):
+        return load().nlse_batch_variant_count(self._h)
+
+    def autotune(self, nsteps=20, force=False):
+        ch = ctypes.c_int()
+        _check(load().nlse_batch_autotune(self._h, int(nsteps), int(bool(force)), ctypes.byref(ch)))
+        return ch.value
