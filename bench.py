@@ -167,6 +167,30 @@ def bench_batch(P, I, steps=1000):
                          "note": "achieved counts only the 2D instances' algorithmic bytes (152 B/point-step)"}}
 
 
+def bench_learned(P, seed=9000):
+    """Coarse (513^2) + learned corrector vs plain runs, all against the 2049^2 plain run at t = 20,
+    on one held-out seed with the committed weights (trained on the GPU by the library's kernels)."""
+    from paper_1109_1027_amd import corrector as K
+    params, scale = K.load_weights()
+    snaps, t_fine = K.fine_trajectory(seed, snapshots=False)
+    R = snaps[-1].cpu().numpy().astype(np.complex128)
+    res = {"seed": seed, "t_fine_s": t_fine, "E": {}, "T": {}}
+    for n in (512, 1024, 1536):
+        out, el, ns = K.plain_run(seed, n)
+        res["E"][n], res["T"][n] = K.rel(out, R), el
+    out, el = K.learned_run(seed, params, scale)
+    res["E_learned"], res["T_learned"] = K.rel(out, R), el
+    summ = K.summarize([res])
+    print(f"[bench] learned: E_plain(513^2) {summ['E_plain'][512]:.3e}, E_learned {summ['E_learned']:.3e}, "
+          f"equal-error speedup {summ['speedup_vs_plain_equal_error']:.2f}x", file=sys.stderr, flush=True)
+    return {"metric": "coarse+learned vs plain at equal L2 error (vs the 2049^2 plain run, t = 20)",
+            "workload": "2D GP, a=0.5 s=-1 omega=0.05, 1-8 vortices + 1e-3 noise, held-out seed; coarse 513^2 "
+                        "with the 3-layer BF16-MFMA conv corrector every 10 steps",
+            **{k: summ[k] for k in ("E_plain", "T_plain_s", "E_learned", "T_learned_s", "T_fine_s", "fit_order_p",
+                                    "n_equal_error", "speedup_vs_plain_equal_error", "speedup_vs_fine",
+                                    "gain_E512_over_learned")}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +203,7 @@ def main():
     ap.add_argument("--precs3d", default="f32,mixed")
     ap.add_argument("--steps3d", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=1000, help="steps of the batched workload (0: skip)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-corrector comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -235,6 +260,8 @@ def main():
         out["gp3d"] = bench_3d(P, I, args)
     if args.batch_steps > 0:
         out["batch"] = bench_batch(P, I, args.batch_steps)
+    if not args.no_learned:
+        out["learned"] = bench_learned(P)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec)

@@ -180,6 +180,60 @@ int nlse_batch_get_variant(const nlse_batch *b);
 int nlse_batch_autotune(nlse_batch *b, int64_t nsteps, int force, int *chosen);
 void nlse_batch_destroy(nlse_batch *b);
 
+/* ------------------------------------------------------ learned corrector --
+ * A 3-layer 3x3 convolutional network that corrects a coarse 2D field every few
+ * RK4 steps: Psi <- Psi + scale (Y0 + i Y1) on interior nodes, with
+ *   A0 = bf16(features(Psi)), 8 channels per node: Re Psi, Im Psi, 16 Re(h^2 L Psi),
+ *        16 Im(h^2 L Psi), |Psi|^2, V/4, 0, 0  (L: five-point Laplacian, zero outside),
+ *   A1 = bf16(silu(conv(A0, W1) + b1)), A2 = bf16(silu(conv(A1, W2) + b2)) (32 channels),
+ *   Y  = conv(A2, W3) + b3 (2 channels, FP32), zero padding at the grid edge.
+ * Weights are FP32 masters rounded to bf16 for the BF16 MFMA units (FP32 accumulate).
+ * Parameter vector (nlse_corr_param_count() floats): W1[32][9][8] b1[32] W2[32][9][32]
+ * b2[32] W3[2][9][32] b3[2], tap t = 3(dy+1) + (dx+1).  Dense field arguments are
+ * device pointers to complex64 [batch][H][W], ordered on the corrector's stream.
+ * A corrector is used on one stream at a time; its workspace is reused by every call. */
+typedef struct nlse_corr nlse_corr;
+
+int32_t nlse_corr_param_count(void);
+/* Workspace for fields of H x W nodes and up to max_batch fields per call; V: host
+ * potential [H][W] (the V channel of the features), may be NULL for V = 0. */
+int nlse_corr_create(nlse_corr **out, int32_t H, int32_t W, int32_t max_batch, const double *V, void *stream);
+/* Host FP32 parameters and the output scale; resets the Adam moments. */
+int nlse_corr_set_params(nlse_corr *m, const float *params, double scale);
+int nlse_corr_get_params(nlse_corr *m, float *params);
+/* Network output Y (before scaling) for `batch` fields: y_out device FP32 [batch][H][W][2]. */
+int nlse_corr_infer(nlse_corr *m, const void *psi, int32_t batch, float *y_out);
+/* Training on pairs (pred, ref): pred = coarse field after the coarse steps, ref = the
+ * reference (restricted fine) field at the same time.  Loss = mean over interior nodes
+ * and both channels of (Y - (ref - pred)/scale)^2.  nlse_corr_grads returns the FP32
+ * gradient of the loss (host array, may be NULL) and the loss; nlse_corr_train_step
+ * also applies one Adam step (beta 0.9 / 0.999, eps 1e-8) with learning rate lr. */
+int nlse_corr_grads(nlse_corr *m, const void *pred, const void *ref, int32_t batch, float *grads, double *loss);
+int nlse_corr_train_step(nlse_corr *m, const void *pred, const void *ref, int32_t batch, double lr, double *loss);
+/* smooth = R in 1..4: the training target is (ref - pred) filtered by the binomial
+ * kernel of width 2R + 1 along each axis (C(2R, k) / 4^R: [1 2 1]/4, [1 4 6 4 1]/16, ...),
+ * so the network learns only resolved-scale corrections; 0: unfiltered.
+ * NLSE_E_INVAL outside 0..4. */
+int nlse_corr_set_target_filter(nlse_corr *m, int32_t smooth);
+/* Training-input augmentation: Gaussian noise of standard deviation sigma (per real and
+ * imaginary part, interior nodes) added to pred before its features are formed; the
+ * target still uses the unperturbed pred.  Counter-based (splitmix64 + Box-Muller) from
+ * seed and the Adam step, so a training run is reproducible.  sigma = 0 disables it.
+ * Inference (nlse_corr_infer / apply / step_corrected) never adds noise. */
+int nlse_corr_set_augment(nlse_corr *m, double sigma, uint64_t seed);
+/* One correction of a 2D context's current field (its grid must be H x W nodes and its
+ * stream the corrector's). */
+int nlse_corr_apply(nlse_corr *m, nlse_ctx *c);
+/* nsteps RK4 steps of size dt with a correction after every `every` steps. */
+int nlse_step_corrected(nlse_ctx *c, nlse_corr *m, int64_t nsteps, double dt, int32_t every);
+void nlse_corr_destroy(nlse_corr *m);
+
+/* Injection restriction of a dense square complex field (device pointers, stream-ordered):
+ * dst[y][x] = src[f y][f x], src of src_n intervals (complex64 if src_prec = NLSE_F32,
+ * else complex128), dst complex64 of dst_n = src_n / f intervals. */
+int nlse_inject(const void *src, int32_t src_prec, int64_t src_n, void *dst, int64_t dst_n, int32_t factor,
+                void *stream);
+
 #ifdef __cplusplus
 }
 #endif

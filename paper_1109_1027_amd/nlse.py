@@ -40,7 +40,11 @@ EXPORTS = ["nlse_create", "nlse_set_field", "nlse_step", "nlse_get_field", "nlse
            "nlse_batch_create", "nlse_batch_count", "nlse_batch_set_field", "nlse_batch_get_field",
            "nlse_batch_set_dt", "nlse_batch_max_dt", "nlse_batch_mass", "nlse_batch_step", "nlse_batch_sync",
            "nlse_batch_variant_count", "nlse_batch_set_variant", "nlse_batch_get_variant",
-           "nlse_batch_autotune", "nlse_batch_destroy"]
+           "nlse_batch_autotune", "nlse_batch_destroy",
+           "nlse_corr_param_count", "nlse_corr_create", "nlse_corr_set_params", "nlse_corr_get_params",
+           "nlse_corr_infer", "nlse_corr_grads", "nlse_corr_train_step", "nlse_corr_apply",
+           "nlse_step_corrected", "nlse_corr_destroy", "nlse_inject", "nlse_corr_set_target_filter",
+           "nlse_corr_set_augment"]
 
 _lib = None
 
@@ -85,8 +89,23 @@ def load():
     L.nlse_batch_autotune.argtypes = [vp, i64, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     L.nlse_batch_destroy.argtypes = [vp]
     L.nlse_batch_destroy.restype = None
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.nlse_corr_param_count.argtypes = []
+    L.nlse_corr_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(dbl), vp]
+    L.nlse_corr_set_params.argtypes = [vp, fp, dbl]
+    L.nlse_corr_get_params.argtypes = [vp, fp]
+    L.nlse_corr_infer.argtypes = [vp, vp, i32, vp]
+    L.nlse_corr_grads.argtypes = [vp, vp, vp, i32, fp, ctypes.POINTER(dbl)]
+    L.nlse_corr_train_step.argtypes = [vp, vp, vp, i32, dbl, ctypes.POINTER(dbl)]
+    L.nlse_corr_apply.argtypes = [vp, vp]
+    L.nlse_step_corrected.argtypes = [vp, vp, i64, dbl, i32]
+    L.nlse_corr_destroy.argtypes = [vp]
+    L.nlse_corr_destroy.restype = None
+    L.nlse_inject.argtypes = [vp, i32, i64, vp, i64, i32, vp]
+    L.nlse_corr_set_target_filter.argtypes = [vp, i32]
+    L.nlse_corr_set_augment.argtypes = [vp, dbl, ctypes.c_uint64]
     for f in EXPORTS:
-        if f not in ("nlse_destroy", "nlse_last_error", "nlse_batch_destroy"):
+        if f not in ("nlse_destroy", "nlse_last_error", "nlse_batch_destroy", "nlse_corr_destroy"):
             getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -188,6 +207,10 @@ class Solver:
     # ---- time stepping and diagnostics
     def step(self, nsteps, dt):
         _check(load().nlse_step(self._h, int(nsteps), float(dt)))
+
+    def step_corrected(self, corrector, nsteps, dt, every=10):
+        """nsteps RK4 steps with a learned correction after every `every` steps."""
+        _check(load().nlse_step_corrected(self._h, corrector._h, int(nsteps), float(dt), int(every)))
 
     def sync(self):
         _check(load().nlse_sync(self._h))
@@ -340,3 +363,93 @@ class Batch:
         ch = ctypes.c_int()
         _check(load().nlse_batch_autotune(self._h, int(nsteps), int(bool(force)), ctypes.byref(ch)))
         return ch.value
+
+
+class Corrector:
+    """The learned coarse-grid corrector (3-layer 3x3 conv, BF16 MFMA, FP32 accumulate).
+
+    H, W: nodes of the fields it corrects; V: potential on those nodes (numpy [H, W]) or None.
+    Field arguments are torch complex64 GPU tensors of shape [batch, H, W] (or [H, W])."""
+
+    def __init__(self, H, W, max_batch=4, V=None, stream="current"):
+        L = load()
+        self.H, self.W, self.max_batch = int(H), int(W), int(max_batch)
+        self.stream = _current_stream() if stream == "current" else stream
+        self._V = None if V is None else np.ascontiguousarray(V, dtype=np.float64).reshape(H, W)
+        vptr = None if self._V is None else self._V.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h_ = ctypes.c_void_p()
+        _check(L.nlse_corr_create(ctypes.byref(h_), self.H, self.W, self.max_batch, vptr, self.stream))
+        self._h = h_
+        self.nparam = L.nlse_corr_param_count()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().nlse_corr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, scale):
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        if p.size != self.nparam:
+            raise ValueError(f"expected {self.nparam} parameters")
+        _check(load().nlse_corr_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), float(scale)))
+        self.scale = float(scale)
+
+    def set_augment(self, sigma, seed=0):
+        _check(load().nlse_corr_set_augment(self._h, float(sigma), int(seed)))
+
+    def set_target_filter(self, smooth):
+        _check(load().nlse_corr_set_target_filter(self._h, int(smooth)))
+
+    def get_params(self):
+        p = np.empty(self.nparam, dtype=np.float32)
+        _check(load().nlse_corr_get_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return p
+
+    def _fields(self, t):
+        import torch
+        if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("fields must be contiguous complex64 GPU tensors")
+        b = 1 if t.dim() == 2 else t.shape[0]
+        if t.shape[-2:] != (self.H, self.W) or b > self.max_batch:
+            raise ValueError("field shape does not match the corrector")
+        return b
+
+    def infer(self, psi):
+        import torch
+        b = self._fields(psi)
+        y = torch.empty((b, self.H, self.W, 2), dtype=torch.float32, device=psi.device)
+        _check(load().nlse_corr_infer(self._h, ctypes.c_void_p(psi.data_ptr()), b, ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def grads(self, pred, ref):
+        b = self._fields(pred)
+        g = np.empty(self.nparam, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(load().nlse_corr_grads(self._h, ctypes.c_void_p(pred.data_ptr()), ctypes.c_void_p(ref.data_ptr()), b,
+                                      g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, pred, ref, lr):
+        b = self._fields(pred)
+        loss = ctypes.c_double()
+        _check(load().nlse_corr_train_step(self._h, ctypes.c_void_p(pred.data_ptr()), ctypes.c_void_p(ref.data_ptr()),
+                                           b, float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def apply(self, solver):
+        _check(load().nlse_corr_apply(self._h, solver._h))
+
+
+def inject(src, src_n, dst, factor, stream="current"):
+    """dst[y, x] = src[factor y, factor x] for dense square complex GPU tensors (dst complex64)."""
+    import torch
+    prec = PREC["f32"] if src.dtype == torch.complex64 else PREC["f64"]
+    st = _current_stream() if stream == "current" else stream
+    _check(load().nlse_inject(ctypes.c_void_p(src.data_ptr()), prec, int(src_n), ctypes.c_void_p(dst.data_ptr()),
+                              int(src_n) // int(factor), int(factor), st))

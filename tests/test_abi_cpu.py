@@ -51,3 +51,11 @@ def test_no_gpu_gives_error_not_crash():
         assert e.code in (-4, -5)
     else:
         raise AssertionError("expected an error without a GPU")
+
+
+def test_committed_corrector_weights_load():
+    import numpy as np
+    from paper_1109_1027_amd import corrector as K
+    p, scale = K.load_weights()
+    assert p.dtype == np.float32 and p.size == 32 * 9 * 8 + 32 + 32 * 9 * 32 + 32 + 2 * 9 * 32 + 2
+    assert np.all(np.isfinite(p)) and 0 < scale < 1
