@@ -15,6 +15,13 @@
 // while plane z is computed, so a plane never waits a full memory round trip.
 // Barriers only order LDS (they wait on LDS counters, not on loads in flight).
 //
+// The kernel is bound by instruction issue as much as by memory, so all
+// addressing is 32-bit element offsets computed once per thread (fields of up to
+// 2^31 elements; the launcher checks) and advanced by one plane stride per z
+// step; every validity test that does not depend on z is hoisted out of the
+// march, the z tests are block-uniform, and the RK4 stage is a template
+// parameter so each stage loads only what it uses.
+//
 // Face closure values D^a_b (boundary-face nodes) are the Dirichlet constants of
 // launch_boundary_d; see stage2d.hip for why the per-axis and single-storage
 // forms then coincide.
@@ -25,8 +32,8 @@ namespace nlse {
 template <typename T, typename U> struct same3_t { static constexpr bool v = false; };
 template <typename T> struct same3_t<T, T> { static constexpr bool v = true; };
 
-template <typename IN, typename R, typename M, int TYB, int TZ>
-__global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int64_t tiles_x, int64_t tiles_y)
+template <typename IN, typename R, typename M, int TYB, int TZ, int STAGE>
+__global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tiles_x, int tiles_y)
 {
     constexpr int W = 64, NT = 64 * TYB;
     static_assert(NT >= 4 * W, "y-halo load needs at least 256 threads");
@@ -35,17 +42,20 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int64_t 
     __shared__ C<R> sdy[TYB + 2][W];
 
     const int t = threadIdx.x, tx = t & 63, ty = t >> 6;
-    const Layout L = A.L;
-    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t bx = lb % tiles_x, by = (lb / tiles_x) % tiles_y, bz = lb / (tiles_x * tiles_y);
-    const int64_t x0 = 1 + W * bx, y0 = 1 + TYB * by, z0 = 1 + TZ * bz;
-    const int64_t x = x0 + tx, y = y0 + ty;
-    const bool col_ok = x <= L.nx && y <= L.ny;
-    const bool upd_col = x < L.nx && y < L.ny;
+    const int nx = (int)A.L.nx, ny = (int)A.L.ny, nz = (int)A.L.nz;
+    const int px = (int)A.L.px, ox = (int)A.L.ox;
+    const int plane = px * (int)A.L.py;
+    const int lb = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = lb % tiles_x, by = (lb / tiles_x) % tiles_y, bz = lb / (tiles_x * tiles_y);
+    const int x0 = 1 + W * bx, y0 = 1 + TYB * by, z0 = 1 + TZ * bz;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool col_ok = x <= nx && y <= ny;
+    const bool upd_col = x < nx && y < ny;
+    const bool xface = col_ok && x == nx, yface = col_ok && y == ny;
+    const int cidx = y * px + x + ox;                    // own column, plane 0
 
     const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
     const R ck = (R)A.c.ck, two = (R)2;
-    const int stage = A.stage;
     const C<IN> *in = (const C<IN> *)A.in;
     const C<R> *DBx = (const C<R> *)A.DB[0];
     const C<R> *DBy = (const C<R> *)A.DB[1];
@@ -55,110 +65,114 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int64_t 
     C<R> *K = (C<R> *)A.K;
     C<R> *out = (C<R> *)A.out;
     constexpr bool in_is_r = same3_t<IN, R>::v;
-    const int64_t fx = (L.nz + 1) * (L.ny + 1), fy = (L.nz + 1) * (L.nx + 1), fz = (L.ny + 1) * (L.nx + 1);
+    const int fx = (nz + 1) * (ny + 1), fy = (nz + 1) * (nx + 1), fz = (ny + 1) * (nx + 1);
 
-    auto ld = [&](int64_t xx, int64_t yy, int64_t zz) -> C<R> {
-        if (xx < 0 || xx > L.nx || yy < 0 || yy > L.ny || zz < 0 || zz > L.nz) return czero<R>();
-        return cvt<R, IN>(in[L.idx(xx, yy, zz)]);
+    // halo roles, fixed for the whole march
+    const bool hx_role = t < 4 * TYB;
+    int hx_idx = 0, hx_pos_r = 0, hx_pos_c = 0;
+    bool hx_ok = false;
+    if (hx_role) {
+        const int r = t >> 2, k = t & 3;
+        const int hc = x0 + (k == 0 ? -2 : k == 1 ? -1 : k == 2 ? W : W + 1), hr = y0 + r;
+        hx_ok = hc >= 0 && hc <= nx && hr <= ny;
+        hx_idx = hr * px + hc + ox;
+        hx_pos_r = r + 2;
+        hx_pos_c = k == 0 ? 0 : k == 1 ? 1 : k == 2 ? W + 2 : W + 3;
+    }
+    const bool hy_role = t < 4 * W;
+    int hy_idx = 0, hy_pos_r = 0, hy_pos_c = 0;
+    bool hy_ok = false;
+    if (hy_role) {
+        const int k = t >> 6, c = t & 63;
+        const int hr = y0 + (k == 0 ? -2 : k == 1 ? -1 : k == 2 ? TYB : TYB + 1), hc = x0 + c;
+        hy_ok = hr >= 0 && hr <= ny && hc <= nx;
+        hy_idx = hr * px + hc + ox;
+        hy_pos_r = k == 0 ? 0 : k == 1 ? 1 : k == 2 ? TYB + 2 : TYB + 3;
+        hy_pos_c = c + 2;
+    }
+    // halo D roles: D^x at columns x0-1 / x0+64 for the TYB rows, D^y at rows y0-1 / y0+TYB
+    const bool hdx_role = t < 2 * TYB;
+    const int hdx_r = t >> 1, hdx_side = t & 1;
+    const int hdx_col = hdx_side ? x0 + W : x0 - 1, hdx_row = y0 + hdx_r;
+    const int hdx_face = (hdx_role && hdx_row <= ny) ? (hdx_col == 0 ? 0 : hdx_col == nx ? 1 : -1) : -1;
+    const bool hdy_role = t < 2 * W;
+    const int hdy_side = t >> 6, hdy_c = t & 63;
+    const int hdy_row = hdy_side ? y0 + TYB : y0 - 1, hdy_col = x0 + hdy_c;
+    const int hdy_face = (hdy_role && hdy_col <= nx) ? (hdy_row == 0 ? 0 : hdy_row == ny ? 1 : -1) : -1;
+
+    auto ldp = [&](int zz, int idx, bool ok) -> C<R> {   // Psi_in at plane zz (block-uniform bounds)
+        return (ok && zz >= 0 && zz <= nz) ? cvt<R, IN>(in[zz * plane + idx]) : czero<R>();
     };
     auto d2 = [&](const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> {
         return cscale<R>(ih2, cadd<R>(csub<R>(p, cscale<R>(two, c)), m));
     };
-    // D^z at plane zz of the own column from the queue values, or the face closure
-    auto dz_at = [&](int64_t zz, const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> {
+    auto dz_at = [&](int zz, const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> {
         if (!col_ok) return czero<R>();
-        if (zz == 0) return DBz[y * (L.nx + 1) + x];
-        if (zz == L.nz) return DBz[fz + y * (L.nx + 1) + x];
+        if (zz == 0) return DBz[y * (nx + 1) + x];
+        if (zz == nz) return DBz[fz + y * (nx + 1) + x];
         return d2(m, c, p);
     };
-    // halo of plane zz: x-halo (4 columns x TYB rows), y-halo (4 rows x 64 columns)
-    auto ld_hx = [&](int64_t zz) -> C<R> {
-        if (t >= 4 * TYB) return czero<R>();
-        const int r = t >> 2, k = t & 3;
-        return ld(x0 + (k == 0 ? -2 : k == 1 ? -1 : k == 2 ? W : W + 1), y0 + r, zz);
-    };
-    auto ld_hy = [&](int64_t zz) -> C<R> {
-        if (t >= 4 * W) return czero<R>();
-        const int k = t >> 6, c = t & 63;
-        return ld(x0 + c, y0 + (k == 0 ? -2 : k == 1 ? -1 : k == 2 ? TYB : TYB + 1), zz);
-    };
     struct Ops { C<M> pn; C<R> kt; R vv; };
-    auto ld_ops = [&](int64_t zz) -> Ops {
+    auto ld_ops = [&](int zz) -> Ops {
         Ops o;
         o.pn = mk<M>(M(0), M(0));
         o.kt = czero<R>();
         o.vv = R(0);
-        if (upd_col && zz < L.nz) {
-            const int64_t p = L.idx(x, y, zz);
-            if (stage >= 2 || !in_is_r) o.pn = psin[p];
-            if (stage >= 2) o.kt = K[p];
+        if (upd_col && zz < nz) {
+            const int p = zz * plane + cidx;
+            if (STAGE >= 2 || !in_is_r) o.pn = psin[p];
+            if (STAGE >= 2) o.kt = K[p];
             if (V) o.vv = V[p];
         }
         return o;
     };
 
-    // prologue: queue for the first plane, its halo and its update operands
     C<R> q[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) q[k] = col_ok ? ld(x, y, z0 - 2 + k) : czero<R>();
-    C<R> hx = ld_hx(z0), hy = ld_hy(z0);
+    for (int k = 0; k < 5; ++k) q[k] = ldp(z0 - 2 + k, cidx, col_ok);
+    C<R> hx = ldp(z0, hx_idx, hx_ok), hy = ldp(z0, hy_idx, hy_ok);
     Ops ops = ld_ops(z0);
     C<R> dzm = dz_at(z0 - 1, q[0], q[1], q[2]);
     C<R> dz0 = dz_at(z0, q[1], q[2], q[3]);
 
     for (int zi = 0; zi < TZ; ++zi) {
-        const int64_t z = z0 + zi;
-        if (z >= L.nz) break;   // block-uniform
-        // prefetch plane z+1
-        const bool more = (zi + 1 < TZ) && (z + 1 < L.nz);
-        const C<R> q5 = (more && col_ok) ? ld(x, y, z + 3) : czero<R>();
-        const C<R> nhx = more ? ld_hx(z + 1) : czero<R>();
-        const C<R> nhy = more ? ld_hy(z + 1) : czero<R>();
-        const Ops nops = more ? ld_ops(z + 1) : Ops{mk<M>(M(0), M(0)), czero<R>(), R(0)};
-
+        const int z = z0 + zi;
+        if (z >= nz) break;   // block-uniform
+        const bool more = (zi + 1 < TZ) && (z + 1 < nz);
+        C<R> q5 = czero<R>(), nhx = czero<R>(), nhy = czero<R>();
+        Ops nops{mk<M>(M(0), M(0)), czero<R>(), R(0)};
+        if (more) {
+            q5 = ldp(z + 3, cidx, col_ok);
+            nhx = ldp(z + 1, hx_idx, hx_ok);
+            nhy = ldp(z + 1, hy_idx, hy_ok);
+            nops = ld_ops(z + 1);
+        }
         const C<R> dzp = dz_at(z + 1, q[2], q[3], q[4]);
         sp[ty + 2][tx + 2] = q[2];
-        if (t < 4 * TYB) {
-            const int r = t >> 2, k = t & 3;
-            sp[r + 2][k == 0 ? 0 : k == 1 ? 1 : k == 2 ? W + 2 : W + 3] = hx;
-        }
-        if (t < 4 * W) {
-            const int k = t >> 6, c = t & 63;
-            sp[k == 0 ? 0 : k == 1 ? 1 : k == 2 ? TYB + 2 : TYB + 3][c + 2] = hy;
-        }
+        if (hx_role) sp[hx_pos_r][hx_pos_c] = hx;
+        if (hy_role) sp[hy_pos_r][hy_pos_c] = hy;
         __syncthreads();
-        // step 1 in-plane: own D^x, D^y and the one-node halos
-        C<R> dx = d2(sp[ty + 2][tx + 1], sp[ty + 2][tx + 2], sp[ty + 2][tx + 3]);
-        C<R> dy = d2(sp[ty + 1][tx + 2], sp[ty + 2][tx + 2], sp[ty + 3][tx + 2]);
-        if (col_ok && x == L.nx) dx = DBx[fx + z * (L.ny + 1) + y];
-        if (col_ok && y == L.ny) dy = DBy[fy + z * (L.nx + 1) + x];
+        C<R> dx = d2(sp[ty + 2][tx + 1], q[2], sp[ty + 2][tx + 3]);
+        C<R> dy = d2(sp[ty + 1][tx + 2], q[2], sp[ty + 3][tx + 2]);
+        if (xface) dx = DBx[fx + z * (ny + 1) + y];
+        if (yface) dy = DBy[fy + z * (nx + 1) + x];
         sdx[ty][tx + 1] = dx;
         sdy[ty + 1][tx] = dy;
-        if (t < 2 * TYB) {
-            const int r = t >> 1, side = t & 1;
-            const int c = side ? W + 2 : 1;
-            C<R> hdx = d2(sp[r + 2][c - 1], sp[r + 2][c], sp[r + 2][c + 1]);
-            const int64_t hxx = side ? x0 + W : x0 - 1, yy = y0 + r;
-            if (yy <= L.ny) {
-                if (hxx == 0) hdx = DBx[z * (L.ny + 1) + yy];
-                else if (hxx == L.nx) hdx = DBx[fx + z * (L.ny + 1) + yy];
-            }
-            sdx[r][side ? W + 1 : 0] = hdx;
+        if (hdx_role) {
+            const int c = hdx_side ? W + 2 : 1;
+            C<R> hdx = d2(sp[hdx_r + 2][c - 1], sp[hdx_r + 2][c], sp[hdx_r + 2][c + 1]);
+            if (hdx_face >= 0) hdx = DBx[hdx_face * fx + z * (ny + 1) + hdx_row];
+            sdx[hdx_r][hdx_side ? W + 1 : 0] = hdx;
         }
-        if (t < 2 * W) {
-            const int side = t >> 6, c = t & 63;
-            const int r = side ? TYB + 2 : 1;
-            C<R> hdy = d2(sp[r - 1][c + 2], sp[r][c + 2], sp[r + 1][c + 2]);
-            const int64_t yy = side ? y0 + TYB : y0 - 1, xx = x0 + c;
-            if (xx <= L.nx) {
-                if (yy == 0) hdy = DBy[z * (L.nx + 1) + xx];
-                else if (yy == L.ny) hdy = DBy[fy + z * (L.nx + 1) + xx];
-            }
-            sdy[side ? TYB + 1 : 0][c] = hdy;
+        if (hdy_role) {
+            const int r = hdy_side ? TYB + 2 : 1;
+            C<R> hdy = d2(sp[r - 1][hdy_c + 2], sp[r][hdy_c + 2], sp[r + 1][hdy_c + 2]);
+            if (hdy_face >= 0) hdy = DBy[hdy_face * fy + z * (nx + 1) + hdy_col];
+            sdy[hdy_side ? TYB + 1 : 0][hdy_c] = hdy;
         }
         __syncthreads();
         if (upd_col) {
-            const int64_t p = L.idx(x, y, z);
+            const int p = z * plane + cidx;
             const C<R> nb = cadd<R>(cadd<R>(cadd<R>(sdx[ty][tx + 2], sdx[ty][tx]), cadd<R>(sdy[ty + 2][tx], sdy[ty][tx])),
                                     cadd<R>(dzp, dzm));
             const C<R> lap = csub<R>(cscale<R>(c76, cadd<R>(cadd<R>(dx, dy), dz0)), cscale<R>(c112, nb));
@@ -166,12 +180,12 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int64_t 
             const R nl = s * (u.x * u.x + u.y * u.y) - ops.vv;
             const C<R> zz = cadd<R>(cscale<R>(a, lap), cscale<R>(nl, u));
             const C<R> F = mk<R>(-zz.y, zz.x);
-            if (stage == 1) {
+            if (STAGE == 1) {
                 const C<M> base = in_is_r ? cvt<M, R>(u) : ops.pn;
                 K[p] = F;
                 const C<R> inc = cscale<R>(ck, F);
                 out[p] = cvt<R, M>(mk<M>(base.x + (M)inc.x, base.y + (M)inc.y));
-            } else if (stage <= 3) {
+            } else if (STAGE <= 3) {
                 K[p] = cadd<R>(ops.kt, cscale<R>(two, F));
                 const C<R> inc = cscale<R>(ck, F);
                 out[p] = cvt<R, M>(mk<M>(ops.pn.x + (M)inc.x, ops.pn.y + (M)inc.y));
@@ -193,26 +207,37 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int64_t 
     }
 }
 
-template <typename IN, typename R, typename M, int TYB, int TZ>
+template <typename IN, typename R, typename M, int TYB, int TZ, int STAGE>
 static hipError_t launch3(const StageArgs &a, hipStream_t st)
 {
     const int64_t tiles_x = (a.L.nx - 1 + 63) / 64;
     const int64_t tiles_y = (a.L.ny - 1 + TYB - 1) / TYB;
     const int64_t tiles_z = (a.L.nz - 1 + TZ - 1) / TZ;
     const int64_t blocks = tiles_x * tiles_y * tiles_z;
-    hipLaunchKernelGGL((stage3d_kernel<IN, R, M, TYB, TZ>), dim3((unsigned)blocks), dim3(64 * TYB), 0, st, a,
-                       tiles_x, tiles_y);
+    hipLaunchKernelGGL((stage3d_kernel<IN, R, M, TYB, TZ, STAGE>), dim3((unsigned)blocks), dim3(64 * TYB), 0, st, a,
+                       (int)tiles_x, (int)tiles_y);
     return hipGetLastError();
+}
+
+template <typename IN, typename R, typename M, int TYB, int TZ>
+static hipError_t launch3s(const StageArgs &a, hipStream_t st)
+{
+    switch (a.stage) {
+    case 1: return launch3<IN, R, M, TYB, TZ, 1>(a, st);
+    case 2: return launch3<IN, R, M, TYB, TZ, 2>(a, st);
+    case 3: return launch3<IN, R, M, TYB, TZ, 3>(a, st);
+    default: return launch3<IN, R, M, TYB, TZ, 4>(a, st);
+    }
 }
 
 template <typename IN, typename R, typename M>
 static hipError_t launch3v(const StageArgs &a, hipStream_t st)
 {
     switch (a.variant) {
-    case 0: return launch3<IN, R, M, 4, 32>(a, st);
-    case 1: return launch3<IN, R, M, 4, 64>(a, st);
-    case 2: return launch3<IN, R, M, 8, 32>(a, st);
-    case 3: return launch3<IN, R, M, 4, 16>(a, st);
+    case 0: return launch3s<IN, R, M, 4, 32>(a, st);
+    case 1: return launch3s<IN, R, M, 4, 64>(a, st);
+    case 2: return launch3s<IN, R, M, 8, 32>(a, st);
+    case 3: return launch3s<IN, R, M, 4, 16>(a, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -221,6 +246,8 @@ int stage3d_variants() { return 4; }
 
 hipError_t launch_stage3d(Prec prec, const StageArgs &a, hipStream_t st)
 {
+    // 32-bit element offsets: every field (and every face array) must hold < 2^31 elements
+    if (a.L.total >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     switch (prec) {
     case P_F64: return launch3v<double, double, double>(a, st);
     case P_F32: return launch3v<float, float, float>(a, st);
