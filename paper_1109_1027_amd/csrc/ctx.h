@@ -28,11 +28,13 @@ struct nlse_ctx {
     nlse::Prec prec;
     size_t esR, esM, rR;        // bytes: stage complex, master complex, stage real
     void *psi = nullptr, *A = nullptr, *B = nullptr, *K = nullptr, *V = nullptr;
+    void *psi2 = nullptr;       // 2D: second master buffer of the whole-step kernel (swapped with psi)
+    void *V0 = nullptr;         // 2D without potential: zeros, read by the whole-step kernel
     void *DB[3] = {nullptr, nullptr, nullptr};
     double *red = nullptr;      // reduction partials (2 * reduce_partials()) + result slots
     hipStream_t stream = nullptr;
     double kmax = 0.0;
     bool have_field = false;
-    int variant = 0;            // tile-shape variant of the stage kernels
+    int variant = 0;            // kernel variant (tile shape; in 2D also stage vs whole-step kernels)
     std::vector<double> Vhost;  // for host-side MSD closure (1D)
 };

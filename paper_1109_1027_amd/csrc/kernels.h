@@ -34,6 +34,23 @@ int stage2d_variants();
 hipError_t launch_stage3d(Prec prec, const StageArgs &a, hipStream_t st);
 int stage3d_variants();
 
+// 2D whole-step kernel: all four RK4 stages of one step in one launch (see
+// step2d.hip).  Reads the master Psi^n from psi_in and writes the interior of
+// Psi^{n+1} to psi_out, a different buffer whose boundary nodes already hold
+// the (fixed) Dirichlet values.  K_tot and the stage fields stay on chip.
+struct Step2DArgs {
+    const void *psi_in;
+    void *psi_out;
+    const void *V;       // potential (real, stage type); never nullptr (zeros when V = 0)
+    const void *DB[2];   // boundary-face normal second differences (as in StageArgs)
+    Layout L;
+    Coeffs c;            // ck unused
+    double ck[4];        // k/2, k/2, k, k/6
+    int variant;
+};
+hipError_t launch_step2d(Prec prec, const Step2DArgs &a, hipStream_t st);
+int step2d_variants();
+
 // 1D persistent solver: one workgroup holds the whole field on chip and runs
 // nsteps RK4 steps in one launch.
 struct Solve1DArgs {

@@ -1,0 +1,68 @@
+// Point-wise pieces of one 2SHOC-RK4 stage, shared by every 2D kernel.  Every
+// fused multiply-add is written out and automatic contraction is off, so all
+// kernels that use these helpers perform the same roundings in the same order:
+// their results are bit-identical, whatever the tiling or the fusion of stages.
+#pragma once
+
+#include "common.h"
+
+namespace nlse {
+
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Step 1 along one axis: delta^2 Psi = (Psi_{+1} - 2 Psi_0 + Psi_{-1}) / h^2
+// (Sec. 2.1, Eq. 2shoc1d: the second-order central difference).  2 Psi_0 is
+// exact, so the fma rounds Psi_{+1} - 2 Psi_0 once, as the plain expression does.
+template <typename R>
+__device__ __forceinline__ C<R> d2(C<R> lo, C<R> c, C<R> hi, R ih2)
+{
+#pragma clang fp contract(off)
+    return mk<R>((fmar(R(-2), c.x, hi.x) + lo.x) * ih2, (fmar(R(-2), c.y, hi.y) + lo.y) * ih2);
+}
+
+// Step 2 of the per-axis 2D form (Sec. 2.2, Eqs. 2d2shocMs1-2): sum over both axes of
+// D^a - (1/12) delta_a^2 D^a, written as (7/6)(D^x + D^y) - (1/12)(neighbour sums).
+template <typename R>
+__device__ __forceinline__ C<R> lap2(C<R> dx, C<R> dy, C<R> dxl, C<R> dxr, C<R> dyd, C<R> dyu, R c76, R c112)
+{
+#pragma clang fp contract(off)
+    const R ax = dx.x + dy.x, ay = dx.y + dy.y;
+    const R bx = (dxr.x + dxl.x) + (dyu.x + dyd.x), by = (dxr.y + dxl.y) + (dyu.y + dyd.y);
+    return mk<R>(fmar(c76, ax, -(c112 * bx)), fmar(c76, ay, -(c112 * by)));
+}
+
+// Right-hand side of the NLSE (Sec. 1, Eq. NLSE) written as Psi_t = F:
+// F = i [a Lap + (s |Psi|^2 - V) Psi].
+template <typename R>
+__device__ __forceinline__ C<R> rhs(C<R> lap, C<R> u, R v, R a, R s)
+{
+#pragma clang fp contract(off)
+    const R nl = fmar(s, fmar(u.x, u.x, u.y * u.y), -v);
+    const R zx = fmar(nl, u.x, a * lap.x), zy = fmar(nl, u.y, a * lap.y);
+    return mk<R>(-zy, zx);
+}
+
+// K_tot accumulation of stages 2 and 3: K + 2F (2F is exact).
+template <typename R>
+__device__ __forceinline__ C<R> kacc(C<R> k, C<R> F)
+{
+#pragma clang fp contract(off)
+    return mk<R>(fmar(R(2), F.x, k.x), fmar(R(2), F.y, k.y));
+}
+
+// base + ck * F (Sec. 3.1, the array updates of Eq. RK4).  When the master type
+// is wider than the stage type the increment is rounded to the stage type first.
+template <typename R, typename M>
+__device__ __forceinline__ C<M> axpy_m(C<M> base, R ck, C<R> F)
+{
+#pragma clang fp contract(off)
+    if constexpr (sizeof(M) == sizeof(R)) {
+        return mk<M>(fmar(ck, F.x, base.x), fmar(ck, F.y, base.y));
+    } else {
+        const R ix = ck * F.x, iy = ck * F.y;
+        return mk<M>(base.x + (M)ix, base.y + (M)iy);
+    }
+}
+
+}  // namespace nlse

@@ -6,10 +6,13 @@
 //   K     K_tot                   (stage precision)
 //   V     potential               (real, stage precision; absent when V = 0)
 //   DB    boundary-face closure values of the per-axis 2SHOC (2D / 3D)
-// One RK4 step enqueues four fused stage kernels (2D / 3D):
+//   psi2  2D only: a second master buffer for the whole-step kernel
+// With the stage-kernel variants one RK4 step enqueues four fused stage kernels:
 //   S1 psi -> A, S2 A -> B, S3 B -> A, S4 A -> psi
 // The ping-pong keeps every stage's stencil input read-only while the next stage
-// field is written.  1D contexts run all steps in one persistent launch.
+// field is written.  The 2D whole-step variants enqueue one kernel per step,
+// psi -> psi2, and then swap the two pointers.  1D contexts run all steps in
+// one persistent launch.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -17,6 +20,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "ctx.h"
@@ -67,7 +71,7 @@ static int64_t face_nodes(const Layout &L, int axis)
 static void free_ctx(nlse_ctx *c)
 {
     if (!c) return;
-    void *bufs[] = {c->psi, c->A, c->B, c->K, c->V, c->DB[0], c->DB[1], c->DB[2], c->red};
+    void *bufs[] = {c->psi, c->psi2, c->A, c->B, c->K, c->V, c->V0, c->DB[0], c->DB[1], c->DB[2], c->red};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete c;
@@ -79,11 +83,6 @@ static std::map<TuneKey, int> g_tuned;
 static std::mutex g_tuned_mu;
 
 static TuneKey tune_key(const nlse_ctx *c) { return TuneKey(c->p.ndim, (int)c->prec, c->L.nx, c->L.ny, c->L.nz); }
-
-static int variant_count(const nlse_ctx *c)
-{
-    return c->p.ndim == 2 ? stage2d_variants() : c->p.ndim == 3 ? stage3d_variants() : 1;
-}
 
 static hipError_t launch_stage(nlse_ctx *c, int stage, double dt, int variant)
 {
@@ -103,6 +102,50 @@ static hipError_t launch_stage(nlse_ctx *c, int stage, double dt, int variant)
     a.stage = stage;
     a.variant = variant;
     return c->p.ndim == 2 ? launch_stage2d(c->prec, a, c->stream) : launch_stage3d(c->prec, a, c->stream);
+}
+
+// 2D variants: [0, stage2d_variants()) are the stage kernels, the rest the
+// whole-step kernels (their 32-bit offsets need fields below 2^31 elements).
+static bool step2d_ok(const nlse_ctx *c) { return c->p.ndim == 2 && c->L.total < (int64_t(1) << 31); }
+
+static int variant_count(const nlse_ctx *c)
+{
+    if (c->p.ndim == 2) return stage2d_variants() + (step2d_ok(c) ? step2d_variants() : 0);
+    return c->p.ndim == 3 ? stage3d_variants() : 1;
+}
+
+static bool whole_step(const nlse_ctx *c, int variant) { return c->p.ndim == 2 && variant >= stage2d_variants(); }
+
+// One RK4 step of a 2D context with a whole-step variant: psi -> psi2, then swap.
+static hipError_t launch_whole_step(nlse_ctx *c, double dt, int variant)
+{
+    Step2DArgs a;
+    a.psi_in = c->psi;
+    a.psi_out = c->psi2;
+    a.V = c->V ? c->V : c->V0;
+    a.DB[0] = c->DB[0];
+    a.DB[1] = c->DB[1];
+    a.L = c->L;
+    a.c = base_coeffs(c->p);
+    a.ck[0] = dt / 2.0;
+    a.ck[1] = dt / 2.0;
+    a.ck[2] = dt;
+    a.ck[3] = dt / 6.0;
+    a.variant = variant - stage2d_variants();
+    hipError_t e = launch_step2d(c->prec, a, c->stream);
+    if (e == hipSuccess) std::swap(c->psi, c->psi2);
+    return e;
+}
+
+// One RK4 step with the given variant.
+static hipError_t launch_rk4_step(nlse_ctx *c, double dt, int variant)
+{
+    if (whole_step(c, variant)) return launch_whole_step(c, dt, variant);
+    for (int st = 1; st <= 4; ++st) {
+        hipError_t e = launch_stage(c, st, dt, variant);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 extern "C" {
@@ -145,36 +188,39 @@ int nlse_autotune(nlse_ctx *c, int reps, int force, int *chosen)
                 return NLSE_OK;
             }
         }
-        // Time stage-2 launches (A -> B, K updated in place).  They only write K and the
-        // interior of B, which the next RK4 step overwrites before reading, so tuning
-        // leaves the state of the integration untouched.
+        // Time `reps` whole RK4 steps of every variant (twice, keeping the fastest) on a
+        // copy of the field, then put the field back: the integration state is unchanged.
         const double dt = 0.5 * c->kmax;
-        hipEvent_t e0, e1;
-        HIPTRY(hipEventCreate(&e0));
-        HIPTRY(hipEventCreate(&e1));
+        const size_t bytes = (size_t)c->L.total * c->esM;
+        void *save = nullptr;
+        HIPTRY(hipMalloc(&save, bytes));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
         float best = 1e30f;
         int bestv = 0;
-        for (int round = 0; round < 2; ++round) {
-            for (int v = 0; v < nv; ++v) {
-                hipError_t e = launch_stage(c, 2, dt, v);   // warm
-                if (e != hipSuccess) return hipfail(e, "autotune launch");
-                HIPTRY(hipEventRecord(e0, c->stream));
-                for (int r = 0; r < reps; ++r) {
-                    e = launch_stage(c, 2, dt, v);
-                    if (e != hipSuccess) return hipfail(e, "autotune launch");
-                }
-                HIPTRY(hipEventRecord(e1, c->stream));
-                HIPTRY(hipEventSynchronize(e1));
-                float ms;
-                HIPTRY(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) {
+        hipError_t e = hipMemcpyAsync(save, c->psi, bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        for (int round = 0; round < 2 && e == hipSuccess; ++round) {
+            for (int v = 0; v < nv && e == hipSuccess; ++v) {
+                e = launch_rk4_step(c, dt, v);   // warm
+                if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_rk4_step(c, dt, v);
+                if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess && ms < best) {
                     best = ms;
                     bestv = v;
                 }
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->psi, save, bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(save);
+        if (e != hipSuccess) return hipfail(e, "autotune");
         c->variant = bestv;
         std::lock_guard<std::mutex> g(g_tuned_mu);
         g_tuned[tune_key(c)] = bestv;
@@ -223,6 +269,7 @@ int nlse_create(nlse_ctx **out, const nlse_params *p)
         return NLSE_OK;
     };
     int rc = alloc(&c->psi, T * c->esM);
+    if (!rc && p->ndim == 2) rc = alloc(&c->psi2, T * c->esM);
     if (!rc && p->ndim > 1) rc = alloc(&c->A, T * c->esR);
     if (!rc && p->ndim > 1) rc = alloc(&c->B, T * c->esR);
     if (!rc && p->ndim > 1) rc = alloc(&c->K, T * c->esR);
@@ -244,6 +291,7 @@ int nlse_create(nlse_ctx **out, const nlse_params *p)
             if (p->ndim == 1) c->Vhost.assign(p->V, p->V + w);
         }
     }
+    if (!rc && p->ndim == 2 && !p->V) rc = alloc(&c->V0, T * c->rR);   // alloc zero-fills
     if (rc) {
         free_ctx(c);
         return rc;
@@ -262,7 +310,7 @@ void nlse_destroy(nlse_ctx *c)
 int nlse_launches_per_step(const nlse_ctx *c)
 {
     if (!c) return fail(NLSE_E_INVAL, "NULL context");
-    return c->p.ndim == 1 ? 0 : 4;
+    return c->p.ndim == 1 ? 0 : whole_step(c, c->variant) ? 1 : 4;
 }
 
 int nlse_sync(nlse_ctx *c)
@@ -382,6 +430,8 @@ int nlse_set_field(nlse_ctx *c, const void *psi, int on_device)
     if (!c || !psi) return fail(NLSE_E_INVAL, "nlse_set_field: NULL argument");
     int rc = copy_field(c, c->psi, (void *)psi, on_device, true);
     if (rc) return rc;
+    if (c->psi2)   // the whole-step kernel writes interiors only: give psi2 the boundary values
+        HIPTRY(hipMemcpyAsync(c->psi2, c->psi, (size_t)c->L.total * c->esM, hipMemcpyDeviceToDevice, c->stream));
     if (c->p.ndim > 1) {
         HIPTRY(launch_master_to_stage(c->prec, c->psi, c->A, c->L, c->stream));
         HIPTRY(launch_master_to_stage(c->prec, c->psi, c->B, c->L, c->stream));
@@ -430,10 +480,8 @@ int nlse_step(nlse_ctx *c, int64_t nsteps, double dt)
         return NLSE_OK;
     }
     for (int64_t step = 0; step < nsteps; ++step) {
-        for (int st = 1; st <= 4; ++st) {
-            hipError_t e = launch_stage(c, st, dt, c->variant);
-            if (e != hipSuccess) return hipfail(e, "stage kernel launch");
-        }
+        hipError_t e = launch_rk4_step(c, dt, c->variant);
+        if (e != hipSuccess) return hipfail(e, "RK4 step launch");
     }
     return NLSE_OK;
 }

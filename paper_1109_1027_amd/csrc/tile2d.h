@@ -6,6 +6,7 @@
 #pragma once
 
 #include "kernels.h"
+#include "point.h"
 
 namespace nlse {
 
@@ -29,7 +30,7 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
     const bool xnode = valid && x <= L.nx;
 
     const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
-    const R ck = (R)A.c.ck, two = (R)2;
+    const R ck = (R)A.c.ck;
     const int stage = A.stage;
     const C<IN> *in = (const C<IN> *)A.in;
     const C<R> *DBx = (const C<R> *)A.DB[0];
@@ -82,8 +83,7 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
     C<R> dx[RW];
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
-        const C<R> l = lds[wv][r][lane + 1], c = lds[wv][r][lane + 2], rr = lds[wv][r][lane + 3];
-        dx[r] = cscale<R>(ih2, cadd<R>(csub<R>(rr, cscale<R>(two, c)), l));
+        dx[r] = d2<R>(lds[wv][r][lane + 1], lds[wv][r][lane + 2], lds[wv][r][lane + 3], ih2);
         if (xnode && x == L.nx && y0 + r <= L.ny) dx[r] = DBx[(L.ny + 1) + y0 + r];   // face x = nx
     }
 #pragma unroll
@@ -91,8 +91,7 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
     if (valid && lane < 2 * RW) {
         const int r = lane >> 1, side = lane & 1;
         const int c = side ? W + 2 : 1;               // LDS column of x0+64 or x0-1
-        const C<R> l = lds[wv][r][c - 1], m = lds[wv][r][c], rr = lds[wv][r][c + 1];
-        C<R> hdx = cscale<R>(ih2, cadd<R>(csub<R>(rr, cscale<R>(two, m)), l));
+        C<R> hdx = d2<R>(lds[wv][r][c - 1], lds[wv][r][c], lds[wv][r][c + 1], ih2);
         const int64_t hx = side ? x0 + W : x0 - 1;
         const int64_t y = y0 + r;
         if (y <= L.ny) {
@@ -107,7 +106,7 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
 #pragma unroll
     for (int j = 0; j < RW + 2; ++j) {
         const int64_t y = y0 - 1 + j;
-        dy[j] = cscale<R>(ih2, cadd<R>(csub<R>(col[j + 2], cscale<R>(two, col[j + 1])), col[j]));
+        dy[j] = d2<R>(col[j], col[j + 1], col[j + 2], ih2);
         if (xnode && y == 0) dy[j] = DBy[x];
         if (xnode && y == L.ny) dy[j] = DBy[(L.nx + 1) + x];
     }
@@ -118,26 +117,19 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
     for (int r = 0; r < RW; ++r) {
         const int64_t y = y0 + r;
         if (!(xnode && x < L.nx && y < L.ny)) continue;
-        const C<R> dxl = ldx[wv][r][lane], dxr = ldx[wv][r][lane + 2];
-        const C<R> lap = csub<R>(cscale<R>(c76, cadd<R>(dx[r], dy[r + 1])),
-                                 cscale<R>(c112, cadd<R>(cadd<R>(dxr, dxl), cadd<R>(dy[r + 2], dy[r]))));
+        const C<R> lap = lap2<R>(dx[r], dy[r + 1], ldx[wv][r][lane], ldx[wv][r][lane + 2], dy[r], dy[r + 2], c76, c112);
         const C<R> u = col[r + 2];
-        const R nl = s * (u.x * u.x + u.y * u.y) - vv[r];
-        const C<R> z = cadd<R>(cscale<R>(a, lap), cscale<R>(nl, u));
-        const C<R> F = mk<R>(-z.y, z.x);
+        const C<R> F = rhs<R>(lap, u, vv[r], a, s);
         const int64_t p = L.idx(x, y, 0);
         if (stage == 1) {
             const C<M> base = in_is_r ? cvt<M, R>(u) : pn[r];
             K[p] = F;
-            const C<R> inc = cscale<R>(ck, F);
-            out[p] = cvt<R, M>(mk<M>(base.x + (M)inc.x, base.y + (M)inc.y));
+            out[p] = cvt<R, M>(axpy_m<R, M>(base, ck, F));
         } else if (stage <= 3) {
-            K[p] = cadd<R>(kt[r], cscale<R>(two, F));
-            const C<R> inc = cscale<R>(ck, F);
-            out[p] = cvt<R, M>(mk<M>(pn[r].x + (M)inc.x, pn[r].y + (M)inc.y));
+            K[p] = kacc<R>(kt[r], F);
+            out[p] = cvt<R, M>(axpy_m<R, M>(pn[r], ck, F));
         } else {
-            const C<R> inc = cscale<R>(ck, cadd<R>(kt[r], F));
-            psin[p] = mk<M>(pn[r].x + (M)inc.x, pn[r].y + (M)inc.y);
+            psin[p] = axpy_m<R, M>(pn[r], ck, cadd<R>(kt[r], F));
         }
     }
 }
