@@ -1,20 +1,23 @@
-"""Throughput of the fused 2SHOC-RK4 stage kernels on the 2D Gross-Pitaevskii workload.
+"""Throughput of the 2SHOC-RK4 integrator on the 2D Gross-Pitaevskii workload.
 
 Workload: a = 0.5, s = -1, V = 0.5 (0.05)^2 r^2 on [-40, 40]^2, 2048 intervals per axis
 (2049^2 nodes, 2047^2 interior points), Dirichlet 0, vortex in a Thomas-Fermi cloud
 plus 1e-3 seeded complex noise; dt = 0.5 x the stability bound (4.0415e-4).  One
-"step" is one classic RK4 step (four fused stage kernels) over the whole grid.
-Inputs are resident in HBM before the timed region; K steps are timed with HIP
-events on the solver's stream, bracketed by device synchronisation.
+"step" is one classic RK4 step over the whole grid, with the kernel variant the
+library's autotuner picks (the whole-step kernel: one launch per step).  Inputs are
+resident in HBM before the timed region; K steps are timed with HIP events on the
+solver's stream, bracketed by device synchronisation.
 
 Prints one JSON line.  value = interior points x RK4 steps / s / 1e9 (FP64 path).
-roofline: algorithmic bytes of the stage kernel per launch (76 B per interior point
-for complex128: 304 B per point-step over 4 launches) / its mean launch time.
+roofline: the dominant kernel's algorithmic work per launch / its mean launch time.
+The whole-step kernel is bound by vector-ALU issue: achieved = 190 real flops per
+interior point and step (FMA = 2) / launch time, against the vector peak of its type.
+The four-launch stage kernels are timed beside it ("stage_kernels") with their HBM
+roofline (76 B per interior point and launch for complex128).
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -26,37 +29,43 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+import bench_traffic  # noqa: E402
+
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per interior point and RK4 step (4 fused stages, V stored):
+# algorithmic HBM bytes per interior point and RK4 step of the stage kernels (4 launches, V stored):
 #   complex128 17*16 + 4*8 = 304; complex64 17*8 + 4*4 = 152; mixed (complex128 master) 192
 BYTES_PER_POINT_STEP = {"f64": 304, "f32": 152, "mixed": 192}
+# ... and of the whole-step kernel: Psi^n and V read, Psi^{n+1} written
+WHOLE_STEP_BYTES = {"f64": 40, "f32": 20, "mixed": 36}
+# real flops of one RK4 step per interior point (FMA = 2): 4 x 41 for the two step-1
+# differences, step 2 and F, plus 26 for the K_tot and Psi updates
+FLOPS_PER_POINT_STEP = 190
+VECTOR_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "mixed": 157.3}
 METRIC = "2SHOC-RK4 Gpt·steps/s + % HBM peak; coarse+learned vs plain fine at equal L2 err"
-KERNEL_SRC = os.path.join(ROOT, "paper_1109_1027_amd", "csrc", "stage2d.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage2d_gp2d_2048.json")
 
 
-def kernel_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
-
-
-def measured_traffic(prec, launches_ratio=1.0):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they match this kernel source."""
+def measured_traffic(kind, prec):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they match the kernel's sources."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(bench_traffic.traffic_file(kind)))
     except (OSError, ValueError):
         return None
-    if t.get("source_sha") != kernel_sha() or prec not in t.get("per_launch_bytes", {}):
+    if t.get("source_sha") != bench_traffic.source_sha(kind) or prec not in t.get("per_launch_bytes", {}):
         return None
     return t["per_launch_bytes"][prec]
 
 
-def time_solver(P, spec, prec, steps, warmup):
-    """Time `steps` RK4 steps after `warmup` untimed ones; HIP events on the solver's stream."""
+def time_solver(P, spec, prec, steps, warmup, variant=None):
+    """Time `steps` RK4 steps after `warmup` untimed ones; HIP events on the solver's stream.
+    variant None: the library's autotuner picks the kernel variant (untimed)."""
     import torch
     s = P.Solver.from_spec(spec, prec=prec)
     s.set_field(spec.psi0)
     dt = 0.5 * s.max_dt()
-    variant = s.autotune(reps=5)       # tile shape chosen by the library's autotuner (untimed)
+    if variant is None:
+        variant = s.autotune(reps=20)
+    else:
+        s.variant = variant
     s.step(warmup, dt)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -73,6 +82,23 @@ def time_solver(P, spec, prec, steps, warmup):
     launches = s.launches_per_step() * steps
     s.close()
     return ms, wall, launches, dt, mass, variant
+
+
+def best_stage_variant(P, spec, prec, steps=100):
+    """Fastest of the four-launch stage-kernel variants (for the stage-kernel comparison)."""
+    s = P.Solver.from_spec(spec, prec=prec)
+    cands = []
+    for v in range(s.variant_count()):
+        s.variant = v
+        if s.launches_per_step() == 4:
+            cands.append(v)
+    s.close()
+    best = None
+    for v in cands:
+        ms = time_solver(P, spec, prec, steps, 5, variant=v)[0]
+        if best is None or ms < best[0]:
+            best = (ms, v)
+    return best[1]
 
 
 def copy_ceiling_gbs():
@@ -222,19 +248,45 @@ def main():
     for prec in precs:
         ms, wall, launches, dt, mass, variant = time_solver(P, spec, prec, args.steps, args.warmup)
         gpts = npts * args.steps / (ms * 1e-3) / 1e9
-        per_launch_bytes = BYTES_PER_POINT_STEP[prec] * npts / 4
         avg_launch_s = ms * 1e-3 / launches
-        achieved = per_launch_bytes / avg_launch_s / 1e9
-        tr = measured_traffic(prec)
-        res[prec] = {
-            "value": gpts, "ms_per_step": ms / args.steps, "wall_s": wall, "dt": dt, "mass_end": mass,
-            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
-                         "kernel": "nlse::stage2d_kernel", "algorithmic_bytes_per_launch": per_launch_bytes,
-                         "avg_launch_us": avg_launch_s * 1e6, "tile_variant": variant},
-        }
-        print(f"[bench] {prec}: {gpts:.2f} Gpt*steps/s, {ms / args.steps:.4f} ms/step, "
-              f"{achieved:.0f} GB/s algorithmic ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)",
+        whole = launches == args.steps
+        if whole:
+            flops = FLOPS_PER_POINT_STEP * npts
+            bytes_ = WHOLE_STEP_BYTES[prec] * npts
+            achieved = flops / avg_launch_s / 1e12
+            roof = {"bound": "alu", "achieved": achieved, "peak": VECTOR_PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                    "frac": achieved / VECTOR_PEAK_TFLOPS[prec], "traffic": measured_traffic("step2d", prec),
+                    "kernel": "nlse::step2d_kernel", "algorithmic_flops_per_launch": flops,
+                    "algorithmic_bytes_per_launch": bytes_, "hbm_gbs_algorithmic": bytes_ / avg_launch_s / 1e9,
+                    "avg_launch_us": avg_launch_s * 1e6, "tile_variant": variant}
+            note = (f"{achieved:.2f} TFLOP/s algorithmic ({100 * roof['frac']:.1f}% of the {prec} vector peak), "
+                    f"{roof['hbm_gbs_algorithmic']:.0f} GB/s of HBM")
+        else:
+            bytes_ = BYTES_PER_POINT_STEP[prec] * npts / 4
+            achieved = bytes_ / avg_launch_s / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("stage2d", prec),
+                    "kernel": "nlse::stage2d_kernel", "algorithmic_bytes_per_launch": bytes_,
+                    "avg_launch_us": avg_launch_s * 1e6, "tile_variant": variant}
+            note = f"{achieved:.0f} GB/s algorithmic ({100 * roof['frac']:.1f}% of HBM peak)"
+        res[prec] = {"value": gpts, "ms_per_step": ms / args.steps, "wall_s": wall, "dt": dt, "mass_end": mass,
+                     "launches_per_step": launches // args.steps, "roofline": roof}
+        print(f"[bench] {prec}: {gpts:.2f} Gpt*steps/s, {ms / args.steps:.4f} ms/step, {note}",
+              file=sys.stderr, flush=True)
+        # the four-launch stage kernels on the same workload, with their HBM roofline
+        sv = best_stage_variant(P, spec, prec)
+        ms_s, _, launches_s, _, _, _ = time_solver(P, spec, prec, args.steps, args.warmup, variant=sv)
+        per_launch = BYTES_PER_POINT_STEP[prec] * npts / 4
+        avg_s = ms_s * 1e-3 / launches_s
+        ach_s = per_launch / avg_s / 1e9
+        res[prec]["stage_kernels"] = {
+            "value": npts * args.steps / (ms_s * 1e-3) / 1e9, "ms_per_step": ms_s / args.steps,
+            "roofline": {"bound": "hbm", "achieved": ach_s, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach_s / HBM_PEAK_GBS, "traffic": measured_traffic("stage2d", prec),
+                         "kernel": "nlse::stage2d_kernel", "algorithmic_bytes_per_launch": per_launch,
+                         "avg_launch_us": avg_s * 1e6, "tile_variant": sv}}
+        print(f"[bench] {prec} stage kernels: {res[prec]['stage_kernels']['value']:.2f} Gpt*steps/s, "
+              f"{ach_s:.0f} GB/s algorithmic ({100 * ach_s / HBM_PEAK_GBS:.1f}% of HBM peak)",
               file=sys.stderr, flush=True)
     main_prec = precs[0]
     out = {
@@ -248,7 +300,8 @@ def main():
                    "grid_nodes": [args.n + 1, args.n + 1], "interior_points": npts,
                    "precision": main_prec, "parallelism": "single GPU"},
         "roofline": res[main_prec]["roofline"],
-        "variants": {p: {k: v for k, v in r.items() if k in ("value", "ms_per_step", "roofline")}
+        "stage_kernels": res[main_prec]["stage_kernels"],
+        "variants": {p: {k: v for k, v in r.items() if k in ("value", "ms_per_step", "roofline", "stage_kernels")}
                      for p, r in res.items() if p != main_prec},
     }
     try:

@@ -1,9 +1,12 @@
-"""Turn two rocprofv3 counter runs of bench.py into per-launch HBM traffic of the 2D stage kernel.
+"""Turn two rocprofv3 counter runs of bench.py into per-launch HBM traffic of a 2D kernel.
 
-Usage: python bench_traffic.py <fetch_counter_collection.csv> <write_counter_collection.csv>
-Counters are KiB per dispatch.  Each is scaled by what it reads for the plain copy kernel
-of known size that bench.py runs (torch copy_ of a 1 GiB float64 tensor: 1 GiB read and
-1 GiB written), then averaged over all stage launches of each precision.
+Usage: python bench_traffic.py <step2d|stage2d> <fetch_counter_collection.csv> <write_counter_collection.csv>
+
+Counters are KiB per dispatch.  Each is scaled by what it reads for the plain copy kernel of
+known size that bench.py runs (torch copy_ of a 1 GiB float64 tensor: 1 GiB read and 1 GiB
+written), then averaged over all launches of the kernel for each precision.  The result goes
+to profiles/traffic_<kind>_gp2d_2048.json together with a hash of the kernel's sources;
+bench.py reports it only while the sources still match.
 """
 import collections
 import csv
@@ -13,9 +16,29 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(ROOT, "paper_1109_1027_amd", "csrc")
 GIB = float(1 << 30)
-KEYS = {"f64": ["stage2d_kernel<double, double, double"], "f32": ["stage2d_kernel<float, float, float"],
-        "mixed": ["stage2d_kernel<double, float, double", "stage2d_kernel<float, float, double"]}
+
+# source files each kernel is compiled from (its .hip and every header it includes)
+SOURCES = {"stage2d": ["stage2d.hip", "tile2d.h", "point.h", "common.h", "kernels.h"],
+           "step2d": ["step2d.hip", "point.h", "common.h", "kernels.h"]}
+KEYS = {"stage2d": {"f64": ["stage2d_kernel<double, double, double"], "f32": ["stage2d_kernel<float, float, float"],
+                    "mixed": ["stage2d_kernel<double, float, double", "stage2d_kernel<float, float, double"]},
+        "step2d": {"f64": ["step2d_kernel<double, double"], "f32": ["step2d_kernel<float, float"],
+                   "mixed": ["step2d_kernel<float, double"]}}
+NAMES = {"stage2d": "nlse::stage2d_kernel (mean over the four RK4-stage launches)",
+         "step2d": "nlse::step2d_kernel (one launch per RK4 step)"}
+
+
+def traffic_file(kind):
+    return os.path.join(ROOT, "profiles", f"traffic_{kind}_gp2d_2048.json")
+
+
+def source_sha(kind):
+    h = hashlib.sha256()
+    for f in SOURCES[kind]:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def per_kernel(path, cname):
@@ -26,34 +49,32 @@ def per_kernel(path, cname):
     return d
 
 
-def main(fetch_csv, write_csv):
+def main(kind, fetch_csv, write_csv):
     F, W = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
     big = lambda vals: [v for v in vals if v > 0.25 * GIB]
     cf, cw = big(F["__amd_rocclr_copyBuffer"]), big(W["__amd_rocclr_copyBuffer"])
     fF, fW = GIB / (sum(cf) / len(cf)), GIB / (sum(cw) / len(cw))
     res, raw = {}, {}
-    for prec, keys in KEYS.items():
+    for prec, keys in KEYS[kind].items():
         fv = [v for k in F for key in keys if key in k for v in F[k]]
         wv = [v for k in W for key in keys if key in k for v in W[k]]
         if not fv:
             continue
-        raw[prec] = {"fetch_bytes": sum(fv) / len(fv), "write_bytes": sum(wv) / len(wv)}
+        raw[prec] = {"fetch_bytes": sum(fv) / len(fv), "write_bytes": sum(wv) / len(wv), "launches": len(fv)}
         res[prec] = fF * raw[prec]["fetch_bytes"] + fW * raw[prec]["write_bytes"]
-    src = os.path.join(ROOT, "paper_1109_1027_amd", "csrc", "stage2d.hip")
-    out = {"kernel": "nlse::stage2d_kernel (mean over the four RK4-stage launches)",
-           "workload": "2D GP, 2049^2 nodes, bench.py defaults",
-           "source_sha": hashlib.sha256(open(src, "rb").read()).hexdigest()[:16],
+    out = {"kernel": NAMES[kind], "workload": "2D GP, 2049^2 nodes, bench.py defaults",
+           "source_sha": source_sha(kind), "sources": SOURCES[kind],
            "per_launch_bytes": res, "raw_counter_bytes": raw,
            "scale_factors": {"FETCH_SIZE": fF, "WRITE_SIZE": fW,
                              "calibration": "torch copy_ of a 1 GiB float64 tensor: 1 GiB read, 1 GiB written"},
            "commands": [
                "cd /tmp && rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/prof_fetch -o fetch --output-format csv "
-               "-- python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline",
+               "-- python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned",
                "cd /tmp && rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/prof_write -o write --output-format csv "
-               "-- python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline"]}
-    json.dump(out, open(os.path.join(ROOT, "profiles", "traffic_stage2d_gp2d_2048.json"), "w"), indent=1)
+               "-- python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned"]}
+    json.dump(out, open(traffic_file(kind), "w"), indent=1)
     print(json.dumps(out, indent=1))
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], sys.argv[2])
+    main(sys.argv[1], sys.argv[2], sys.argv[3])

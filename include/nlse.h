@@ -127,25 +127,29 @@ void nlse_destroy(nlse_ctx *c);
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *nlse_last_error(void);
 
-/* Number of kernel launches one RK4 step enqueues for this context (4 for the
- * tiled 2D/3D stage kernels; 1D contexts advance all steps in one launch and
- * report 0).  For throughput accounting. */
+/* Number of kernel launches one RK4 step enqueues for this context with its current
+ * variant: 4 for the 2D/3D stage kernels, 1 for the 2D whole-step kernels; 1D contexts
+ * advance all steps in one launch and report 0.  For throughput accounting. */
 int nlse_launches_per_step(const nlse_ctx *c);
 
-/* Tile-shape variants of the 2D / 3D stage kernels (2D: 64 columns x 8, 4 or 16 rows per
- * wave; 3D: 64 x 4 or 64 x 8 columns marching 16, 32 or 64 planes).  Every variant
- * computes bit-identical fields; they differ only in speed.  1D contexts have one. */
+/* Kernel variants.  2D: 0-2 are the stage kernels (one launch per RK4 stage, tiles of
+ * 64 columns x 8, 4 or 16 rows per wave); 3-6 the whole-step kernels (one launch per RK4
+ * step, Sec. 3.1 with all four stages fused; a wave walks a 64-column strip down a segment
+ * of 29, 20, 38 or 56 rows; offered when the padded field has fewer than 2^31 elements).
+ * 3D: stage kernels with 64 x 4 or 64 x 8 column tiles marching 16, 32 or 64 planes.
+ * Every variant computes bit-identical fields; they differ only in speed.  1D contexts
+ * have one. */
 int nlse_variant_count(const nlse_ctx *c);
 int nlse_set_variant(nlse_ctx *c, int variant);   /* NLSE_E_INVAL if out of range */
 int nlse_get_variant(const nlse_ctx *c);
 
-/* Autotuner: times `reps` stage launches of every variant on this context's own
- * arrays (twice, keeping the fastest), selects the fastest and caches the choice for
- * the process under (ndim, precision, n).  Later calls reuse the cached choice unless
- * force != 0.  Needs a field (nlse_set_field); leaves the integration state unchanged
- * (it only writes K_tot and a stage field that the next step overwrites before
- * reading).  Waits for the stream.  The chosen variant is returned in *chosen
- * (may be NULL). */
+/* Autotuner: times `reps` RK4 steps of every variant on this context's own arrays
+ * (twice, keeping the fastest), selects the fastest and caches the choice for the
+ * process under (ndim, precision, n).  Later calls reuse the cached choice unless
+ * force != 0.  Needs a field (nlse_set_field).  The field is saved to a temporary
+ * device buffer first and restored afterwards, so the integration state is unchanged;
+ * NLSE_E_NOMEM if that buffer cannot be allocated.  Waits for the stream.  The chosen
+ * variant is returned in *chosen (may be NULL). */
 int nlse_autotune(nlse_ctx *c, int reps, int force, int *chosen);
 
 /* ---------------------------------------------------------------- batches --

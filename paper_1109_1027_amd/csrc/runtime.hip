@@ -193,7 +193,10 @@ int nlse_autotune(nlse_ctx *c, int reps, int force, int *chosen)
         const double dt = 0.5 * c->kmax;
         const size_t bytes = (size_t)c->L.total * c->esM;
         void *save = nullptr;
-        HIPTRY(hipMalloc(&save, bytes));
+        if (hipMalloc(&save, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(NLSE_E_NOMEM, "autotune: no memory for the field copy");
+        }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         float best = 1e30f;
         int bestv = 0;

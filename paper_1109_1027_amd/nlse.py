@@ -245,7 +245,7 @@ class Solver:
         _check(load().nlse_set_variant(self._h, int(v)))
 
     def autotune(self, reps=5, force=False):
-        """Time every tile variant on this problem, keep the fastest; returns its index."""
+        """Time RK4 steps of every kernel variant on this problem, keep the fastest; returns its index."""
         ch = ctypes.c_int()
         _check(load().nlse_autotune(self._h, int(reps), int(bool(force)), ctypes.byref(ch)))
         return ch.value
