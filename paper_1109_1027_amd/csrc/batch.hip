@@ -7,9 +7,10 @@
 // the queue in longest-first order and advance the popped instance through all
 // requested steps before popping again:
 //   - a 1D instance runs entirely on chip (onchip1d.h): HBM is touched twice;
-//   - a 2D instance is swept tile by tile by all waves of the workgroup
-//     (tile2d.h), with a workgroup barrier between RK4 stages; its five arrays
-//     stream through L2 / the Infinity Cache / HBM.
+//   - a 2D instance advances by whole RK4 steps (wave2d.h): the waves of the
+//     workgroup share out its (strip, row segment) tasks, reading Psi^n and V
+//     and writing Psi^{n+1} into the instance's second master buffer, with one
+//     workgroup barrier per step; an odd step count ends with a copy back.
 // Every workgroup leaves the loop when the queue is exhausted, so the grid
 // always drains.  Instances never share memory, so no cross-workgroup
 // synchronisation exists.
@@ -21,7 +22,7 @@
 
 #include "ctx.h"
 #include "onchip1d.h"
-#include "tile2d.h"
+#include "wave2d.h"
 
 using namespace nlse;
 
@@ -29,8 +30,8 @@ namespace nlse {
 
 struct BatchItem {
     Layout L;
-    void *psi, *A, *B, *K;
-    const void *V;
+    void *psi, *psi2;
+    const void *V;      // 2D: never nullptr (zeros when V = 0)
     const void *DB[2];
     Coeffs c;
     double dt;
@@ -49,15 +50,14 @@ __global__ void batch_reset_kernel(int *queue)
     if (threadIdx.x == 0) queue[0] = 0;
 }
 
-template <typename R, typename M, int RW>
+template <typename R, typename M, int Q>
 __global__ __launch_bounds__(BATCH_BS) void batch_kernel(const BatchItem *items, const int *order, int count,
                                                          int *queue, int64_t nsteps)
 {
     extern __shared__ unsigned char smem[];
     __shared__ int s_item;
     constexpr int NPT = BatchNPT<R>::v;
-    using Row = C<R>[RW][TILE_W + 4];
-    using RowD = C<R>[RW][TILE_W + 2];
+    constexpr int FR = wave2d::face_rows<Q>();
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
@@ -79,72 +79,72 @@ __global__ __launch_bounds__(BATCH_BS) void batch_kernel(const BatchItem *items,
             a.msd = I.msd;
             solve1d_onchip<R, M, BATCH_BS, NPT>(a, smem);
         } else {
-            Row *lds = reinterpret_cast<Row *>(smem);
-            RowD *ldx = reinterpret_cast<RowD *>(smem + sizeof(Row) * BATCH_NW);
-            const int64_t tiles_x = (I.L.nx - 1 + TILE_W - 1) / TILE_W;
-            const int64_t tiles = tiles_x * ((I.L.ny - 1 + RW - 1) / RW);
-            const double ck[4] = {dt / 2.0, dt / 2.0, dt, dt / 6.0};
-            void *ins[4] = {I.psi, I.A, I.B, I.A};
-            void *outs[4] = {I.A, I.B, I.A, nullptr};
-            const int wv = threadIdx.x >> 6;
+            auto *sdx = reinterpret_cast<C<R>(*)[2][FR]>(smem);                  // [BATCH_NW][2][FR]
+            auto *sdy = reinterpret_cast<C<R>(*)[2][64]>(smem + sizeof(C<R>) * BATCH_NW * 2 * FR);
+            const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+            const int strips = wave2d::strips(I.L.nx);
+            const int tasks = strips * wave2d::segments<Q>(I.L.ny);
+            Step2DArgs a;
+            a.V = I.V;
+            a.DB[0] = I.DB[0];
+            a.DB[1] = I.DB[1];
+            a.L = I.L;
+            a.c = I.c;
+            a.ck[0] = dt / 2.0;
+            a.ck[1] = dt / 2.0;
+            a.ck[2] = dt;
+            a.ck[3] = dt / 6.0;
+            a.variant = 0;
+            void *cur = I.psi, *nxt = I.psi2;
             for (int64_t step = 0; step < nsteps; ++step) {
-                for (int st = 0; st < 4; ++st) {
-                    StageArgs a;
-                    a.in = ins[st];
-                    a.out = outs[st];
-                    a.psin = I.psi;
-                    a.K = I.K;
-                    a.V = I.V;
-                    a.DB[0] = I.DB[0];
-                    a.DB[1] = I.DB[1];
-                    a.DB[2] = nullptr;
-                    a.L = I.L;
-                    a.c = I.c;
-                    a.c.ck = ck[st];
-                    a.stage = st + 1;
-                    a.variant = 0;
-                    for (int64_t base = 0; base < tiles; base += BATCH_NW) {
-                        if (st == 0)
-                            stage2d_tile<M, R, M, RW, BATCH_NW>(a, base + wv, tiles_x, tiles, lds, ldx);
-                        else
-                            stage2d_tile<R, R, M, RW, BATCH_NW>(a, base + wv, tiles_x, tiles, lds, ldx);
-                    }
-                    __syncthreads();   // this stage's outputs are the next stage's inputs
-                }
+                a.psi_in = cur;
+                a.psi_out = nxt;
+                for (int task = wv; task < tasks; task += BATCH_NW)
+                    wave2d::step2d_wave<R, M, Q>(a, task % strips, task / strips, threadIdx.x & 63, sdx[wv], sdy[wv]);
+                __syncthreads();   // Psi^{n+1} complete before any task reads it
+                void *t = cur;
+                cur = nxt;
+                nxt = t;
+            }
+            if (cur != I.psi) {    // odd step count: the result is in psi2
+                const C<M> *src = (const C<M> *)cur;
+                C<M> *dst = (C<M> *)I.psi;
+                for (int64_t e = threadIdx.x; e < I.L.total; e += BATCH_BS) dst[e] = src[e];
             }
         }
     }
 }
 
-template <typename R, typename M, int RW>
+template <typename R, int Q>
 static size_t batch_lds(int64_t max1d_nodes, bool has2d)
 {
-    size_t l1 = 2 * sizeof(C<R>) * (size_t)max1d_nodes;
-    size_t l2 = has2d ? sizeof(C<R>) * RW * (2 * TILE_W + 6) * BATCH_NW : 0;
+    const size_t l1 = 2 * sizeof(C<R>) * (size_t)max1d_nodes;
+    const size_t l2 = has2d ? sizeof(C<R>) * BATCH_NW * 2 * (wave2d::face_rows<Q>() + 64) : 0;
     return std::max(l1, l2);
 }
 
-template <typename R, typename M, int RW>
-static hipError_t launch_batch_rw(const BatchItem *items, const int *order, int count, int *queue, int64_t nsteps,
-                                  int grid, size_t lds, hipStream_t st)
+template <typename R, typename M, int Q>
+static hipError_t launch_batch_q(const BatchItem *items, const int *order, int count, int *queue, int64_t nsteps,
+                                 int grid, size_t lds, hipStream_t st)
 {
-    (void)hipFuncSetAttribute((const void *)batch_kernel<R, M, RW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)batch_kernel<R, M, Q>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, queue);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((batch_kernel<R, M, RW>), dim3(grid), dim3(BATCH_BS), lds, st, items, order, count, queue,
+    hipLaunchKernelGGL((batch_kernel<R, M, Q>), dim3(grid), dim3(BATCH_BS), lds, st, items, order, count, queue,
                        nsteps);
     return hipGetLastError();
 }
 
-// Variant v selects the 2D tile height: (8, 4) rows per wave for FP32 / mixed,
-// (4, 2) for FP64 (LDS holds 16 waves x RW rows x 134 complex values).
+// Variant v selects the row-segment length of the 2D whole-step tasks: 56 rows
+// (v = 0) or 29 rows (v = 1).
+constexpr int BATCH_VARIANTS = 2;
+
 static size_t batch_lds_for(Prec prec, int variant, int64_t max1d, bool has2d)
 {
-    if (prec == P_F64) return variant == 0 ? batch_lds<double, double, 4>(max1d, has2d)
-                                            : batch_lds<double, double, 2>(max1d, has2d);
-    return variant == 0 ? batch_lds<float, float, 8>(max1d, has2d) : batch_lds<float, float, 4>(max1d, has2d);
+    if (prec == P_F64) return variant == 0 ? batch_lds<double, 8>(max1d, has2d) : batch_lds<double, 5>(max1d, has2d);
+    return variant == 0 ? batch_lds<float, 8>(max1d, has2d) : batch_lds<float, 5>(max1d, has2d);
 }
 
 static hipError_t launch_batch(Prec prec, int variant, const BatchItem *items, const int *order, int count,
@@ -152,14 +152,14 @@ static hipError_t launch_batch(Prec prec, int variant, const BatchItem *items, c
 {
     switch (prec) {
     case P_F64:
-        return variant == 0 ? launch_batch_rw<double, double, 4>(items, order, count, queue, nsteps, grid, lds, st)
-                            : launch_batch_rw<double, double, 2>(items, order, count, queue, nsteps, grid, lds, st);
+        return variant == 0 ? launch_batch_q<double, double, 8>(items, order, count, queue, nsteps, grid, lds, st)
+                            : launch_batch_q<double, double, 5>(items, order, count, queue, nsteps, grid, lds, st);
     case P_F32:
-        return variant == 0 ? launch_batch_rw<float, float, 8>(items, order, count, queue, nsteps, grid, lds, st)
-                            : launch_batch_rw<float, float, 4>(items, order, count, queue, nsteps, grid, lds, st);
+        return variant == 0 ? launch_batch_q<float, float, 8>(items, order, count, queue, nsteps, grid, lds, st)
+                            : launch_batch_q<float, float, 5>(items, order, count, queue, nsteps, grid, lds, st);
     default:
-        return variant == 0 ? launch_batch_rw<float, double, 8>(items, order, count, queue, nsteps, grid, lds, st)
-                            : launch_batch_rw<float, double, 4>(items, order, count, queue, nsteps, grid, lds, st);
+        return variant == 0 ? launch_batch_q<float, double, 8>(items, order, count, queue, nsteps, grid, lds, st)
+                            : launch_batch_q<float, double, 5>(items, order, count, queue, nsteps, grid, lds, st);
     }
 }
 
@@ -210,10 +210,8 @@ static int upload_items(nlse_batch *b)
         std::memset(&it, 0, sizeof it);
         it.L = c->L;
         it.psi = c->psi;
-        it.A = c->A;
-        it.B = c->B;
-        it.K = c->K;
-        it.V = c->V;
+        it.psi2 = c->psi2;
+        it.V = c->V ? c->V : c->V0;
         it.DB[0] = c->DB[0];
         it.DB[1] = c->DB[1];
         it.c = base_coeffs(c->p);
@@ -259,6 +257,11 @@ int nlse_batch_create(nlse_batch **out, const nlse_params *items, int32_t count)
         if (rc) {
             batch_free(b);
             return rc;
+        }
+        if (items[i].ndim == 2 && c->L.total >= (int64_t(1) << 31)) {   // 32-bit offsets in wave2d.h
+            nlse_destroy(c);
+            batch_free(b);
+            return fail(NLSE_E_UNSUPPORTED, "2D instance too large for the batched launch");
         }
         b->ctx.push_back(c);
         b->dt.push_back(0.0);
@@ -338,12 +341,12 @@ int nlse_batch_set_dt(nlse_batch *b, int32_t i, double dt)
     return NLSE_OK;
 }
 
-int nlse_batch_variant_count(const nlse_batch *b) { return b ? 2 : fail(NLSE_E_INVAL, "NULL batch"); }
+int nlse_batch_variant_count(const nlse_batch *b) { return b ? BATCH_VARIANTS : fail(NLSE_E_INVAL, "NULL batch"); }
 
 int nlse_batch_set_variant(nlse_batch *b, int variant)
 {
     if (!b) return fail(NLSE_E_INVAL, "NULL batch");
-    if (variant < 0 || variant > 1) return fail(NLSE_E_INVAL, "variant out of range");
+    if (variant < 0 || variant >= BATCH_VARIANTS) return fail(NLSE_E_INVAL, "variant out of range");
     b->variant = variant;
     return NLSE_OK;
 }
@@ -421,7 +424,7 @@ int nlse_batch_autotune(nlse_batch *b, int64_t nsteps, int force, int *chosen)
         return fail(NLSE_E_HIP, "hipEventCreate");
     }
     hipError_t he = copy_all(true);
-    for (int v = 0; v < 2 && he == hipSuccess && !rc; ++v) {
+    for (int v = 0; v < BATCH_VARIANTS && he == hipSuccess && !rc; ++v) {
         b->variant = v;
         he = hipEventRecord(e0, b->stream);
         if (he == hipSuccess) rc = nlse_batch_step(b, nsteps);

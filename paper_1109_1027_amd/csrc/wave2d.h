@@ -1,0 +1,164 @@
+// One wave's share of the 2D whole-step RK4 kernel (shared by the stand-alone
+// whole-step kernel of step2d.hip and the batched persistent kernel): the wave
+// advances the interior of one (48-column strip, row segment) task of Psi^n to
+// Psi^{n+1}.  See step2d.hip for the scheme.  Contains no barrier; the caller
+// provides the wave's private LDS staging for the boundary-face values.
+#pragma once
+
+#include "kernels.h"
+#include "point.h"
+
+namespace nlse {
+namespace wave2d {
+
+constexpr int SW = 48;     // output columns per strip
+constexpr int HALO = 8;    // two rows (columns) per stage
+
+template <int Q> constexpr int seg_rows() { return 9 * Q - 2 * HALO; }   // output rows per segment
+template <int Q> constexpr int face_rows() { return 9 * Q + HALO; }      // rows jb-8 .. jb+9Q-1
+
+__host__ __device__ inline int strips(int64_t nx) { return (int)((nx - 1 + SW - 1) / SW); }
+template <int Q> __host__ __device__ inline int segments(int64_t ny) { return (int)((ny - 1 + seg_rows<Q>() - 1) / seg_rows<Q>()); }
+
+// DPP wave shifts: wave_shr:1 delivers lane i-1's value to lane i, wave_shl:1
+// lane i+1's; lanes shifted in from outside the wave read zero (bound_ctrl).
+__device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ __forceinline__ float lane_prev(float v) { return __int_as_float(dpp_prev(__float_as_int(v))); }
+__device__ __forceinline__ float lane_next(float v) { return __int_as_float(dpp_next(__float_as_int(v))); }
+__device__ __forceinline__ double lane_prev(double v)
+{
+    return __hiloint2double(dpp_prev(__double2hiint(v)), dpp_prev(__double2loint(v)));
+}
+__device__ __forceinline__ double lane_next(double v)
+{
+    return __hiloint2double(dpp_next(__double2hiint(v)), dpp_next(__double2loint(v)));
+}
+template <typename R>
+__device__ __forceinline__ C<R> clane_prev(C<R> v) { return mk<R>(lane_prev(v.x), lane_prev(v.y)); }
+template <typename R>
+__device__ __forceinline__ C<R> clane_next(C<R> v) { return mk<R>(lane_next(v.x), lane_next(v.y)); }
+
+// sdx: [2][face_rows<Q>()] (D^x on the faces x = 0 and x = nx for the task's
+// rows), sdy: [2][64] (D^y on the faces y = 0 and y = ny for its columns);
+// wave-private LDS, rewritten by every call.  strip < strips(nx) and
+// seg < segments<Q>(ny), wave-uniform; the field has < 2^31 elements.
+template <typename R, typename M, int Q>
+__device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int seg, int lane,
+                                            C<R> (*sdx)[face_rows<Q>()], C<R> (*sdy)[64])
+{
+    constexpr int SEG = seg_rows<Q>();
+    constexpr int FR = face_rows<Q>();
+    __builtin_amdgcn_wave_barrier();        // earlier reads of the staging come first
+    const int nx = (int)A.L.nx, ny = (int)A.L.ny, px = (int)A.L.px, ox = (int)A.L.ox;
+    const int xs = 1 + SW * strip - HALO;   // column of lane 0
+    const int x = xs + lane;
+    const bool xin = x >= 0 && x <= nx;
+    const bool xint = x >= 1 && x < nx;
+    const bool xface = x == 0 || x == nx;
+    const bool wlane = xint && lane >= HALO && lane < HALO + SW;
+    const bool has_face = xs <= 0 || xs + 63 >= nx;   // wave-uniform
+    const int y0 = 1 + SEG * seg, y1 = min(y0 + SEG, ny);
+    const int jb = y0 - HALO;               // row of Psi^n that enters at t = 0
+
+    const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
+    R ck[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ck[i] = (R)A.ck[i];
+    const C<M> *__restrict__ pin = (const C<M> *)A.psi_in;
+    C<M> *__restrict__ pout = (C<M> *)A.psi_out;
+    const R *__restrict__ V = (const R *)A.V;
+    const C<R> *__restrict__ DBx = (const C<R> *)A.DB[0];
+    const C<R> *__restrict__ DBy = (const C<R> *)A.DB[1];
+
+    sdy[0][lane] = xin ? DBy[x] : czero<R>();
+    sdy[1][lane] = xin ? DBy[nx + 1 + x] : czero<R>();
+    if (has_face) {
+        for (int i = lane; i < FR; i += 64) {
+            const int r = jb - HALO + i;
+            const bool ok = r >= 0 && r <= ny;
+            sdx[0][i] = ok ? DBx[r] : czero<R>();
+            sdx[1][i] = ok ? DBx[ny + 1 + r] : czero<R>();
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    C<R> U[4][3], D[4][3], Kq[9];
+    C<M> P[9];
+    R Vq[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        Kq[i] = czero<R>();
+        P[i] = mk<M>(M(0), M(0));
+        Vq[i] = R(0);
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) U[st][i] = D[st][i] = czero<R>();
+
+    // Row loads are unconditional, with the address clamped into the field: the
+    // number of loads in flight never depends on the path, so waiting for a
+    // prefetched row leaves the next row's loads outstanding.  Lanes and rows
+    // outside the grid thus hold copies of edge values; they feed no interior
+    // node (the face closures replace every D they would enter).
+    const int xc = min(max(x, 0), nx);
+    auto load_row = [&](int y, C<M> &pv, R &vv) {
+        const int o = min(max(y, 0), ny) * px + xc + ox;
+        pv = pin[o];
+        vv = V[o];
+    };
+    C<M> pf;
+    R vf;
+    load_row(jb, pf, vf);
+
+#pragma unroll 1
+    for (int g = 0; g < Q; ++g) {
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            const int t = 9 * g + p;
+            const int j = jb + t;
+            P[p] = pf;
+            Vq[p] = vf;
+            load_row(j + 1, pf, vf);        // prefetch
+            const int q0 = p % 3, q1 = (p + 1) % 3, q2 = (p + 2) % 3;   // rows m, m-2, m-1
+            C<R> in = cvt<R, M>(P[p]);
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int m = j - 2 * st;   // newest input row of this stage
+                U[st][q0] = in;
+                C<R> dy = d2<R>(U[st][q1], U[st][q2], U[st][q0], ih2);   // D^y at row m-1
+                if (m - 1 == 0) dy = sdy[0][lane];
+                if (m - 1 == ny) dy = sdy[1][lane];
+                D[st][q0] = dy;
+                C<R> outv = czero<R>();
+                if (t >= 4 * (st + 1)) {    // earlier output rows feed nothing
+                    const int r = m - 2;    // output row
+                    const int kr = (p + 18 - 2 * (st + 1)) % 9;
+                    const C<R> u = U[st][q1];
+                    C<R> dx = d2<R>(clane_prev<R>(u), u, clane_next<R>(u), ih2);
+                    if (has_face) {
+                        const C<R> f = sdx[x == 0 ? 0 : 1][r - jb + HALO];
+                        if (xface) dx = f;
+                    }
+                    const C<R> lap = lap2<R>(dx, D[st][q2], clane_prev<R>(dx), clane_next<R>(dx), D[st][q1], D[st][q0], c76, c112);
+                    const C<R> F = rhs<R>(lap, u, Vq[kr], a, s);
+                    const bool upd = xint && r >= 1 && r < ny;
+                    if (st == 0) {
+                        Kq[kr] = F;
+                        outv = upd ? cvt<R, M>(axpy_m<R, M>(P[kr], ck[0], F)) : u;
+                    } else if (st < 3) {
+                        Kq[kr] = kacc<R>(Kq[kr], F);
+                        outv = upd ? cvt<R, M>(axpy_m<R, M>(P[kr], ck[st], F)) : u;
+                    } else if (wlane && r >= y0 && r < y1) {
+                        pout[r * px + x + ox] = axpy_m<R, M>(P[kr], ck[3], cadd<R>(Kq[kr], F));
+                    }
+                }
+                in = outv;
+            }
+        }
+    }
+}
+
+}  // namespace wave2d
+}  // namespace nlse
