@@ -118,7 +118,7 @@ __global__ __launch_bounds__(BATCH_BS) void batch_kernel(const BatchItem *items,
 template <typename R, int Q>
 static size_t batch_lds(int64_t max1d_nodes, bool has2d)
 {
-    const size_t l1 = 2 * sizeof(C<R>) * (size_t)max1d_nodes;
+    const size_t l1 = max1d_nodes > 0 ? onchip1d_lds<R, BATCH_BS>() : 0;
     const size_t l2 = has2d ? sizeof(C<R>) * BATCH_NW * 2 * (wave2d::face_rows<Q>() + 64) : 0;
     return std::max(l1, l2);
 }

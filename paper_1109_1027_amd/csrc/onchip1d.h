@@ -1,135 +1,175 @@
 // On-chip 1D 2SHOC-RK4 solver body (shared by the stand-alone 1D kernel and the
-// batched persistent kernel).  One workgroup of BS threads holds a whole field of
-// up to BS * NPT nodes: Psi^n, K_tot and V in registers of the owning thread
-// (node i belongs to thread i % BS), the stage field and D in LDS.  See
-// solve1d.hip for the per-stage phases.
+// batched persistent kernel).  One workgroup of BS threads holds a whole field
+// of up to BS * NPT nodes and runs all requested RK4 steps; HBM is touched only
+// to load Psi^n at the start and store it at the end.
+//
+// Layout.  Thread t owns npt consecutive nodes i = t*npt - sh + j, j < npt, with
+// npt = max(3, ceil((n+1)/BS)) and a shift sh in {0, 1} chosen so that each
+// boundary node shares its thread with its interior neighbour (node 0 is never
+// a thread's last node, node n never a thread's first).  Psi^n (master type),
+// K_tot, V, the stage field and D of the owned nodes live in registers.  Per
+// stage (Sec. 2.1 Eqs. 2shoc1d-2shoc1d2, Sec. 3.1-3.2):
+//   1. the end nodes of the stage field are exchanged with the neighbouring
+//      threads: DPP lane shifts inside a wave, LDS across waves (barrier);
+//   2. D = delta^2 Psi on the owned nodes; boundary D_b by the Dirichlet rule
+//      (Eq. dbc_lap) or the MSD rule (Eq. msdbc_lap, from D_{b-1});
+//   3. the end values of D are exchanged the same way (barrier);
+//   4. Lap (Eq. 2shoc1d2) and F on interior nodes; boundary F_b: Dirichlet 0
+//      (Eq. dbc_ut) or MSD i Im(F_{b-1}/Psi_{b-1}) Psi_b (Eq. msdbc_ut);
+//   5. the RK4 array operations of the stage (Eq. RK4) on every node that moves.
 #pragma once
 
+#include "dpp.h"
 #include "kernels.h"
+#include "point.h"
 
 namespace nlse {
 
-template <typename R>
-__device__ __forceinline__ C<R> lap1d(const C<R> *sD, int64_t i, R c76, R c112)
+// LDS the solver needs: the cross-wave exchange slots.
+template <typename R, int BS>
+constexpr size_t onchip1d_lds() { return sizeof(C<R>) * 2 * (BS / 64) * 2; }
+
+// Largest field (nodes) the solver holds; the caller guarantees n + 1 <= this.
+template <int BS, int NPT>
+constexpr int64_t onchip1d_max_nodes() { return (int64_t)BS * NPT; }
+
+// End values of the neighbouring threads of an array of npt owned slots: prev = last
+// slot of thread t-1, next = first slot of thread t+1 (DPP inside the wave, the LDS
+// slots `edge` [wave][first, last] across waves).  Contains a workgroup barrier.
+template <typename R, int NPT, int NWV>
+__device__ __forceinline__ void exchange1d(const C<R> (&v)[NPT], int npt, int lane, int wv, C<R> (*edge)[2],
+                                           C<R> &prev, C<R> &next)
 {
-    return csub<R>(cscale<R>(c76, sD[i]), cscale<R>(c112, cadd<R>(sD[i + 1], sD[i - 1])));
+    C<R> last = v[0];
+#pragma unroll
+    for (int j = 1; j < NPT; ++j)
+        if (j == npt - 1) last = v[j];
+    const C<R> first = v[0];
+    prev = clane_prev<R>(last);
+    next = clane_next<R>(first);
+    if (lane == 0) edge[wv][0] = first;
+    if (lane == 63) edge[wv][1] = last;
+    __syncthreads();
+    if (lane == 0 && wv > 0) prev = edge[wv - 1][1];
+    if (lane == 63 && wv < NWV - 1) next = edge[wv + 1][0];
 }
 
-// smem_raw: 2 (n + 1) stage-precision complex values of LDS.
 template <typename R, typename M, int BS, int NPT>
 __device__ void solve1d_onchip(const Solve1DArgs &A, unsigned char *smem_raw)
 {
-    const int64_t n = A.L.nx;                 // nodes 0..n
-    C<R> *sin = (C<R> *)smem_raw;             // stage field
-    C<R> *sD = sin + (n + 1);                 // step-1 array
-    const int t = threadIdx.x;
-    constexpr int BS1D = BS;
+    static_assert(BS % 64 == 0 && NPT >= 3, "whole waves, at least three nodes per thread");
+    constexpr int NWV = BS / 64;
+    C<R>(*edge)[NWV][2] = reinterpret_cast<C<R>(*)[NWV][2]>(smem_raw);   // [exchange][wave][first, last]
+    const int n = __builtin_amdgcn_readfirstlane((int)A.L.nx);   // nodes 0..n
+    const int npt = max(3, (n + 1 + BS - 1) / BS);
+    const int sh = (n % npt == 0) ? 1 : 0;   // BS * npt >= n + 1 + sh holds (see the layout note)
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int i0 = t * npt - sh;             // node of slot 0
+    const int tn = (n + sh) / npt, jn = (n + sh) % npt;   // owner and slot of node n (jn >= 1)
+    const bool msd = __builtin_amdgcn_readfirstlane(A.msd) != 0;
+
     const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
-    const R ia = (R)A.c.ia, two = (R)2;
+    const R ia = (R)A.c.ia;
     const R k2 = (R)A.k2, kk = (R)A.k, k6 = (R)A.k6;
-    const bool msd = A.msd != 0;
     C<M> *gpsi = (C<M> *)A.psin;
     const R *gV = (const R *)A.V;
-    const int64_t o = A.L.ox;
+    const int o = (int)A.L.ox;
 
-    C<M> pn[NPT];
-    C<R> kt[NPT], F[NPT];
-    R vv[NPT];
+    C<M> P[NPT];
+    C<R> U[NPT], K[NPT], D[NPT];   // stage field, K_tot, step-1 values
+    R Vv[NPT];
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
-        const int64_t i = t + (int64_t)j * BS1D;
-        pn[j] = mk<M>(M(0), M(0));
-        kt[j] = czero<R>();
-        F[j] = czero<R>();
-        vv[j] = R(0);
-        if (i <= n) {
-            pn[j] = gpsi[o + i];
-            vv[j] = gV ? gV[o + i] : R(0);
-            sin[i] = cvt<R, M>(pn[j]);
-        }
+        const int i = i0 + j;
+        const bool ok = j < npt && i >= 0 && i <= n;
+        P[j] = ok ? gpsi[o + i] : mk<M>(M(0), M(0));
+        Vv[j] = (ok && gV) ? gV[o + i] : R(0);
+        U[j] = cvt<R, M>(P[j]);
+        K[j] = czero<R>();
+        D[j] = czero<R>();
     }
-    auto Vat = [&](int64_t i) -> R { return gV ? gV[o + i] : R(0); };
-    auto nonl = [&](int64_t i) -> R { const C<R> u = sin[i]; return s * (u.x * u.x + u.y * u.y) - Vat(i); };
-    // second difference at an interior node straight from the stage field
-    auto d2 = [&](int64_t i) -> C<R> {
-        return cscale<R>(ih2, cadd<R>(csub<R>(sin[i + 1], cscale<R>(two, sin[i])), sin[i - 1]));
-    };
-    // F at an interior node from D in LDS
-    auto Fat = [&](int64_t i) -> C<R> {
-        const C<R> u = sin[i];
-        const C<R> z = cadd<R>(cscale<R>(a, lap1d<R>(sD, i, c76, c112)), cscale<R>(nonl(i), u));
-        return mk<R>(-z.y, z.x);
-    };
 
     for (int64_t step = 0; step < A.nsteps; ++step) {
-        for (int stage = 1; stage <= 4; ++stage) {
-            __syncthreads();
-            // phase A: step 1 with its boundary closure
+#pragma unroll 1
+        for (int st = 0; st < 4; ++st) {
+            C<R> up, un;
+            exchange1d<R, NPT, NWV>(U, npt, lane, wv, edge[0], up, un);
+            // step 1 on every owned slot (boundary and out-of-range slots are fixed below or unused)
 #pragma unroll
             for (int j = 0; j < NPT; ++j) {
-                const int64_t i = t + (int64_t)j * BS1D;
-                if (i > n) continue;
-                if (i > 0 && i < n) {
-                    sD[i] = d2(i);
+                if (j >= npt) continue;
+                const C<R> lo = j == 0 ? up : U[j > 0 ? j - 1 : 0];
+                const C<R> hi = j == npt - 1 ? un : U[j + 1 < NPT ? j + 1 : j];
+                D[j] = d2<R>(lo, U[j], hi, ih2);
+            }
+            // boundary D_b: node 0 is slot sh of thread 0, node n slot jn of thread tn
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const bool b0 = t == 0 && j == sh, bn = t == tn && j == jn;
+                if (!(b0 || bn) || j >= npt) continue;
+                // interior neighbour: slot j + 1 for node 0, j - 1 for node n (static indices)
+                const int jp = j + 1 < NPT ? j + 1 : j, jq = j > 0 ? j - 1 : 0;   // constants once unrolled
+                const C<R> ub = U[j];
+                if (!msd) {
+                    D[j] = cscale<R>(-nonlin<R>(ub, Vv[j], s) * ia, ub);
                 } else {
-                    const int64_t bm1 = (i == 0) ? 1 : n - 1;
-                    const C<R> ub = sin[i];
-                    if (!msd) {
-                        sD[i] = cscale<R>(-nonl(i) * ia, ub);
-                    } else {
-                        const C<R> ui = sin[bm1], Di = d2(bm1);
-                        const R den = ui.x * ui.x + ui.y * ui.y;
-                        const R ratio = den != R(0) ? (Di.x * ui.x + Di.y * ui.y) / den : R(0);
-                        sD[i] = cscale<R>(ratio + (nonl(bm1) - nonl(i)) * ia, ub);
-                    }
+                    const C<R> ui = b0 ? U[jp] : U[jq], Di = b0 ? D[jp] : D[jq];
+                    const R vi = b0 ? Vv[jp] : Vv[jq];
+                    const R den = ui.x * ui.x + ui.y * ui.y;
+                    const R ratio = den != R(0) ? (Di.x * ui.x + Di.y * ui.y) / den : R(0);
+                    D[j] = cscale<R>(ratio + (nonlin<R>(ui, vi, s) - nonlin<R>(ub, Vv[j], s)) * ia, ub);
                 }
             }
-            __syncthreads();
-            // phase B: step 2 and F
+            C<R> dp, dn;
+            exchange1d<R, NPT, NWV>(D, npt, lane, wv, edge[1], dp, dn);
+            auto Fint = [&](int j) {   // F at an interior slot from D and the stage field
+                const C<R> dl = j == 0 ? dp : D[j > 0 ? j - 1 : 0];
+                const C<R> dr = j == npt - 1 ? dn : D[j + 1 < NPT ? j + 1 : j];
+                return rhs<R>(lap1<R>(D[j], dl, dr, c76, c112), U[j], Vv[j], a, s);
+            };
+            // MSD boundary F_b, from F_{b-1} of the unchanged stage field (before any update)
+            C<R> Fb = czero<R>();
+            if (msd) {
 #pragma unroll
-            for (int j = 0; j < NPT; ++j) {
-                const int64_t i = t + (int64_t)j * BS1D;
-                F[j] = czero<R>();
-                if (i > n) continue;
-                if (i > 0 && i < n) {
-                    F[j] = Fat(i);
-                } else if (msd) {
-                    const int64_t bm1 = (i == 0) ? 1 : n - 1;
-                    const C<R> Fi = Fat(bm1), ui = sin[bm1], ub = sin[i];
+                for (int j = 0; j < NPT; ++j) {
+                    const bool b0 = t == 0 && j == sh, bn = t == tn && j == jn;
+                    if (!(b0 || bn) || j >= npt) continue;
+                    const int jp = j + 1 < NPT ? j + 1 : j, jq = j > 0 ? j - 1 : 0;   // constants once unrolled
+                    const C<R> Fi = b0 ? Fint(jp) : Fint(jq), ui = b0 ? U[jp] : U[jq], ub = U[j];
                     const R den = ui.x * ui.x + ui.y * ui.y;
                     const R im = den != R(0) ? (Fi.y * ui.x - Fi.x * ui.y) / den : R(0);
-                    F[j] = mk<R>(-im * ub.y, im * ub.x);
+                    Fb = mk<R>(-im * ub.y, im * ub.x);
                 }
             }
-            __syncthreads();
-            // phase C: RK4 array operations of this stage
+            // F and the RK4 array operations of this stage; a slot's update touches only its
+            // own stage value, which no other slot reads any more.  Dirichlet boundary nodes
+            // and slots outside 0..n never change.
+            const R ckst = st == 0 ? k2 : st == 1 ? k2 : st == 2 ? kk : k6;
 #pragma unroll
             for (int j = 0; j < NPT; ++j) {
-                const int64_t i = t + (int64_t)j * BS1D;
-                if (i > n) continue;
-                if ((i == 0 || i == n) && !msd) continue;   // Dirichlet nodes never change
-                C<R> nxt;
-                if (stage == 1) {
-                    kt[j] = F[j];
-                    const C<R> inc = cscale<R>(k2, F[j]);
-                    nxt = cvt<R, M>(mk<M>(pn[j].x + (M)inc.x, pn[j].y + (M)inc.y));
-                } else if (stage <= 3) {
-                    kt[j] = cadd<R>(kt[j], cscale<R>(two, F[j]));
-                    const C<R> inc = cscale<R>(stage == 2 ? k2 : kk, F[j]);
-                    nxt = cvt<R, M>(mk<M>(pn[j].x + (M)inc.x, pn[j].y + (M)inc.y));
+                const int i = i0 + j;
+                if (j >= npt || i < 0 || i > n) continue;
+                const bool bnd = i == 0 || i == n;
+                if (!msd && bnd) continue;
+                const C<R> F = bnd ? Fb : Fint(j);
+                if (st == 0) {
+                    K[j] = F;
+                    U[j] = cvt<R, M>(axpy_m<R, M>(P[j], ckst, F));
+                } else if (st < 3) {
+                    K[j] = kacc<R>(K[j], F);
+                    U[j] = cvt<R, M>(axpy_m<R, M>(P[j], ckst, F));
                 } else {
-                    const C<R> inc = cscale<R>(k6, cadd<R>(kt[j], F[j]));
-                    pn[j] = mk<M>(pn[j].x + (M)inc.x, pn[j].y + (M)inc.y);
-                    nxt = cvt<R, M>(pn[j]);
+                    P[j] = axpy_m<R, M>(P[j], ckst, cadd<R>(K[j], F));
+                    U[j] = cvt<R, M>(P[j]);
                 }
-                sin[i] = nxt;
             }
         }
     }
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
-        const int64_t i = t + (int64_t)j * BS1D;
-        if (i <= n) gpsi[o + i] = pn[j];
+        const int i = i0 + j;
+        if (j < npt && i >= 0 && i <= n) gpsi[o + i] = P[j];
     }
 }
 

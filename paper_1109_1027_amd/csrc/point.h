@@ -32,13 +32,29 @@ __device__ __forceinline__ C<R> lap2(C<R> dx, C<R> dy, C<R> dxl, C<R> dxr, C<R> 
     return mk<R>(fmar(c76, ax, -(c112 * bx)), fmar(c76, ay, -(c112 * by)));
 }
 
+// Step 2 of the 1D form (Sec. 2.1, Eq. 2shoc1d2): (7/6) D_i - (1/12)(D_{i+1} + D_{i-1}).
+template <typename R>
+__device__ __forceinline__ C<R> lap1(C<R> d, C<R> dl, C<R> dr, R c76, R c112)
+{
+#pragma clang fp contract(off)
+    return mk<R>(fmar(c76, d.x, -(c112 * (dr.x + dl.x))), fmar(c76, d.y, -(c112 * (dr.y + dl.y))));
+}
+
+// The nonlinear-minus-potential factor s |Psi|^2 - V of Eq. NLSE.
+template <typename R>
+__device__ __forceinline__ R nonlin(C<R> u, R v, R s)
+{
+#pragma clang fp contract(off)
+    return fmar(s, fmar(u.x, u.x, u.y * u.y), -v);
+}
+
 // Right-hand side of the NLSE (Sec. 1, Eq. NLSE) written as Psi_t = F:
 // F = i [a Lap + (s |Psi|^2 - V) Psi].
 template <typename R>
 __device__ __forceinline__ C<R> rhs(C<R> lap, C<R> u, R v, R a, R s)
 {
 #pragma clang fp contract(off)
-    const R nl = fmar(s, fmar(u.x, u.x, u.y * u.y), -v);
+    const R nl = nonlin<R>(u, v, s);
     const R zx = fmar(nl, u.x, a * lap.x), zy = fmar(nl, u.y, a * lap.y);
     return mk<R>(-zy, zx);
 }

@@ -1,26 +1,15 @@
 // Persistent 1D 2SHOC-RK4 solver: one workgroup keeps the whole field on chip
-// and runs every RK4 step of the call in a single launch.
-//
-// Per stage (Sec. 2.1 Eqs. 2shoc1d-2shoc1d2, Sec. 3.1-3.2):
-//   phase A  D_i = (Psi_{i+1} - 2 Psi_i + Psi_{i-1}) / h^2 on interior nodes (LDS);
-//            boundary D_b: Dirichlet Eq. dbc_lap, or MSD Eq. msdbc_lap, which needs
-//            D_{b-1}: the owner of the boundary node recomputes it from Psi.
-//   phase B  Lap_i = (7/6) D_i - (1/12)(D_{i+1} + D_{i-1});  F_i = i[a Lap_i + (s|Psi_i|^2 - V_i) Psi_i];
-//            boundary F_b: Dirichlet 0 (Eq. dbc_ut); MSD i Im(F_{b-1}/Psi_{b-1}) Psi_b (Eq. msdbc_ut),
-//            with F_{b-1} recomputed by the boundary owner (interior first, boundary second).
-//   phase C  the RK4 array operations of the stage; the next stage field is written to LDS.
-// Psi^n (master precision), K_tot and V stay in registers of the owning thread for
-// the whole launch; LDS holds the stage field and D.  HBM is touched only to load
-// Psi^n at the start and store it at the end.
+// (in registers, see onchip1d.h for the scheme) and runs every RK4 step of the
+// call in a single launch.
 #include "onchip1d.h"
 
 namespace nlse {
 
 template <typename R> struct NPT1D;
-template <> struct NPT1D<double> { static constexpr int v = 5; };   // 5 x 1024 nodes x 32 B = 160 KiB
-template <> struct NPT1D<float> { static constexpr int v = 9; };    // 9 x 1024 nodes x 16 B = 144 KiB
+template <> struct NPT1D<double> { static constexpr int v = 10; };   // 512 threads x 10 nodes
+template <> struct NPT1D<float> { static constexpr int v = 18; };    // 512 threads x 18 nodes
 
-constexpr int BS1D = 1024;
+constexpr int BS1D = 512;
 
 template <typename R, typename M>
 __global__ __launch_bounds__(BS1D) void solve1d_kernel(Solve1DArgs A)
@@ -37,10 +26,7 @@ int64_t solve1d_max_nodes(Prec prec)
 template <typename R, typename M>
 static hipError_t launch1d(const Solve1DArgs &a, hipStream_t st)
 {
-    const size_t lds = 2 * sizeof(C<R>) * (size_t)(a.L.nx + 1);
-    // a launch that asks for more LDS than the device has fails with an error code
-    (void)hipFuncSetAttribute((const void *)solve1d_kernel<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
+    const size_t lds = onchip1d_lds<R, BS1D>();
     hipLaunchKernelGGL((solve1d_kernel<R, M>), dim3(1), dim3(BS1D), lds, st, a);
     return hipGetLastError();
 }

@@ -7,6 +7,7 @@
 
 #include "kernels.h"
 #include "point.h"
+#include "dpp.h"
 
 namespace nlse {
 namespace wave2d {
@@ -19,25 +20,6 @@ template <int Q> constexpr int face_rows() { return 9 * Q + HALO; }      // rows
 
 __host__ __device__ inline int strips(int64_t nx) { return (int)((nx - 1 + SW - 1) / SW); }
 template <int Q> __host__ __device__ inline int segments(int64_t ny) { return (int)((ny - 1 + seg_rows<Q>() - 1) / seg_rows<Q>()); }
-
-// DPP wave shifts: wave_shr:1 delivers lane i-1's value to lane i, wave_shl:1
-// lane i+1's; lanes shifted in from outside the wave read zero (bound_ctrl).
-__device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
-__device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
-__device__ __forceinline__ float lane_prev(float v) { return __int_as_float(dpp_prev(__float_as_int(v))); }
-__device__ __forceinline__ float lane_next(float v) { return __int_as_float(dpp_next(__float_as_int(v))); }
-__device__ __forceinline__ double lane_prev(double v)
-{
-    return __hiloint2double(dpp_prev(__double2hiint(v)), dpp_prev(__double2loint(v)));
-}
-__device__ __forceinline__ double lane_next(double v)
-{
-    return __hiloint2double(dpp_next(__double2hiint(v)), dpp_next(__double2loint(v)));
-}
-template <typename R>
-__device__ __forceinline__ C<R> clane_prev(C<R> v) { return mk<R>(lane_prev(v.x), lane_prev(v.y)); }
-template <typename R>
-__device__ __forceinline__ C<R> clane_next(C<R> v) { return mk<R>(lane_next(v.x), lane_next(v.y)); }
 
 // sdx: [2][face_rows<Q>()] (D^x on the faces x = 0 and x = nx for the task's
 // rows), sdy: [2][64] (D^y on the faces y = 0 and y = ny for its columns);
