@@ -44,15 +44,28 @@ VECTOR_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "mixed": 157.3}
 METRIC = "2SHOC-RK4 Gpt·steps/s + % HBM peak; coarse+learned vs plain fine at equal L2 err"
 
 
-def measured_traffic(kind, prec):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they match the kernel's sources."""
+def measured_traffic(kind, prec, variant):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on this
+    kernel variant and the kernel's sources have not changed since."""
     try:
         t = json.load(open(bench_traffic.traffic_file(kind)))
     except (OSError, ValueError):
         return None
-    if t.get("source_sha") != bench_traffic.source_sha(kind) or prec not in t.get("per_launch_bytes", {}):
+    if t.get("source_sha") != bench_traffic.source_sha(kind):
         return None
-    return t["per_launch_bytes"][prec]
+    ent = t.get("per_launch_bytes", {}).get(prec)
+    if not ent or ent.get("variant") != variant:
+        return None
+    return ent["bytes"]
+
+
+def parse_variants(spec):
+    """"f64:6,f32:3" -> {"f64": 6, "f32": 3}; "" -> {}."""
+    out = {}
+    for item in filter(None, spec.split(",")):
+        k, v = item.split(":")
+        out[k] = int(v)
+    return out
 
 
 def time_solver(P, spec, prec, steps, warmup, variant=None):
@@ -230,6 +243,9 @@ def main():
     ap.add_argument("--steps3d", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=1000, help="steps of the batched workload (0: skip)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-corrector comparison")
+    ap.add_argument("--variant2d", default="", help="force 2D kernel variants per precision, e.g. f64:6,f32:3 "
+                                                    "(default: the library's autotuner)")
+    ap.add_argument("--stage-variant", default="", help="force the stage-kernel comparison variants, e.g. f64:1")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -244,9 +260,11 @@ def main():
     spec = I.config_gp2d(n=args.n)
     npts = spec.interior_points
     precs = args.precs.split(",")
+    force2d, force_stage = parse_variants(args.variant2d), parse_variants(args.stage_variant)
     res = {}
     for prec in precs:
-        ms, wall, launches, dt, mass, variant = time_solver(P, spec, prec, args.steps, args.warmup)
+        ms, wall, launches, dt, mass, variant = time_solver(P, spec, prec, args.steps, args.warmup,
+                                                            variant=force2d.get(prec))
         gpts = npts * args.steps / (ms * 1e-3) / 1e9
         avg_launch_s = ms * 1e-3 / launches
         whole = launches == args.steps
@@ -255,7 +273,7 @@ def main():
             bytes_ = WHOLE_STEP_BYTES[prec] * npts
             achieved = flops / avg_launch_s / 1e12
             roof = {"bound": "alu", "achieved": achieved, "peak": VECTOR_PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                    "frac": achieved / VECTOR_PEAK_TFLOPS[prec], "traffic": measured_traffic("step2d", prec),
+                    "frac": achieved / VECTOR_PEAK_TFLOPS[prec], "traffic": measured_traffic("step2d", prec, variant),
                     "kernel": "nlse::step2d_kernel", "algorithmic_flops_per_launch": flops,
                     "algorithmic_bytes_per_launch": bytes_, "hbm_gbs_algorithmic": bytes_ / avg_launch_s / 1e9,
                     "avg_launch_us": avg_launch_s * 1e6, "tile_variant": variant}
@@ -265,7 +283,7 @@ def main():
             bytes_ = BYTES_PER_POINT_STEP[prec] * npts / 4
             achieved = bytes_ / avg_launch_s / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("stage2d", prec),
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("stage2d", prec, variant),
                     "kernel": "nlse::stage2d_kernel", "algorithmic_bytes_per_launch": bytes_,
                     "avg_launch_us": avg_launch_s * 1e6, "tile_variant": variant}
             note = f"{achieved:.0f} GB/s algorithmic ({100 * roof['frac']:.1f}% of HBM peak)"
@@ -274,7 +292,7 @@ def main():
         print(f"[bench] {prec}: {gpts:.2f} Gpt*steps/s, {ms / args.steps:.4f} ms/step, {note}",
               file=sys.stderr, flush=True)
         # the four-launch stage kernels on the same workload, with their HBM roofline
-        sv = best_stage_variant(P, spec, prec)
+        sv = force_stage[prec] if prec in force_stage else best_stage_variant(P, spec, prec)
         ms_s, _, launches_s, _, _, _ = time_solver(P, spec, prec, args.steps, args.warmup, variant=sv)
         per_launch = BYTES_PER_POINT_STEP[prec] * npts / 4
         avg_s = ms_s * 1e-3 / launches_s
@@ -282,7 +300,7 @@ def main():
         res[prec]["stage_kernels"] = {
             "value": npts * args.steps / (ms_s * 1e-3) / 1e9, "ms_per_step": ms_s / args.steps,
             "roofline": {"bound": "hbm", "achieved": ach_s, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": ach_s / HBM_PEAK_GBS, "traffic": measured_traffic("stage2d", prec),
+                         "frac": ach_s / HBM_PEAK_GBS, "traffic": measured_traffic("stage2d", prec, sv),
                          "kernel": "nlse::stage2d_kernel", "algorithmic_bytes_per_launch": per_launch,
                          "avg_launch_us": avg_s * 1e6, "tile_variant": sv}}
         print(f"[bench] {prec} stage kernels: {res[prec]['stage_kernels']['value']:.2f} Gpt*steps/s, "

@@ -1,6 +1,9 @@
 """Turn two rocprofv3 counter runs of bench.py into per-launch HBM traffic of a 2D kernel.
 
-Usage: python bench_traffic.py <step2d|stage2d> <fetch_counter_collection.csv> <write_counter_collection.csv>
+Usage: python bench_traffic.py <step2d|stage2d> <variant2d> <stage_variant> <fetch_collection.csv> <write_collection.csv>
+
+<variant2d> and <stage_variant> are the per-precision kernel variants the counter runs of bench.py
+were given (--variant2d, --stage-variant), e.g. f64:6,f32:3,mixed:3.
 
 Counters are KiB per dispatch.  Each is scaled by what it reads for the plain copy kernel of
 known size that bench.py runs (torch copy_ of a 1 GiB float64 tensor: 1 GiB read and 1 GiB
@@ -49,7 +52,9 @@ def per_kernel(path, cname):
     return d
 
 
-def main(kind, fetch_csv, write_csv):
+def main(kind, variant2d, stage_variant, fetch_csv, write_csv):
+    variants = variant2d if kind == "step2d" else stage_variant
+    var = {k: int(v) for k, v in (item.split(":") for item in variants.split(","))}
     F, W = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
     big = lambda vals: [v for v in vals if v > 0.25 * GIB]
     cf, cw = big(F["__amd_rocclr_copyBuffer"]), big(W["__amd_rocclr_copyBuffer"])
@@ -61,20 +66,20 @@ def main(kind, fetch_csv, write_csv):
         if not fv:
             continue
         raw[prec] = {"fetch_bytes": sum(fv) / len(fv), "write_bytes": sum(wv) / len(wv), "launches": len(fv)}
-        res[prec] = fF * raw[prec]["fetch_bytes"] + fW * raw[prec]["write_bytes"]
+        res[prec] = {"bytes": fF * raw[prec]["fetch_bytes"] + fW * raw[prec]["write_bytes"],
+                     "variant": var.get(prec)}
     out = {"kernel": NAMES[kind], "workload": "2D GP, 2049^2 nodes, bench.py defaults",
            "source_sha": source_sha(kind), "sources": SOURCES[kind],
            "per_launch_bytes": res, "raw_counter_bytes": raw,
            "scale_factors": {"FETCH_SIZE": fF, "WRITE_SIZE": fW,
                              "calibration": "torch copy_ of a 1 GiB float64 tensor: 1 GiB read, 1 GiB written"},
            "commands": [
-               "cd /tmp && rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/prof_fetch -o fetch --output-format csv "
-               "-- python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned",
-               "cd /tmp && rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/prof_write -o write --output-format csv "
-               "-- python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned"]}
+               f"cd /tmp && rocprofv3 --pmc {c} -d $R/gpurun_out/prof_{c} -o pmc --output-format csv "
+               f"-- python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned "
+               f"--variant2d {variant2d} --stage-variant {stage_variant}" for c in ("FETCH_SIZE", "WRITE_SIZE")]}
     json.dump(out, open(traffic_file(kind), "w"), indent=1)
     print(json.dumps(out, indent=1))
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], sys.argv[2], sys.argv[3])
+    main(*sys.argv[1:6])

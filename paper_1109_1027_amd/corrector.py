@@ -64,6 +64,13 @@ def _solver(n, V, prec="f32"):
     return N.Solver(2, n, 2 * L_HALF / n, A_COEF, S_COEF, V, prec=prec)
 
 
+def _tuned(s):
+    """Let the library pick the fastest kernel variant for this grid (all variants give
+    bit-identical fields; the choice is cached per grid for the process).  Untimed."""
+    s.autotune(reps=10)
+    return s
+
+
 def fine_trajectory(seed, snapshots=True, noise=1e-3):
     """Run the fine problem of `seed` to T_END; return the injected coarse snapshots
     [N_COARSE_STEPS/EVERY + 1, 513, 513] (complex64, on the GPU) and the run time."""
@@ -71,6 +78,7 @@ def fine_trajectory(seed, snapshots=True, noise=1e-3):
     g, psi, V = fine_problem(seed, noise=noise)
     s = _solver(N_FINE, V)
     s.set_field(psi.astype(np.complex64))
+    _tuned(s)
     nc = N_FINE // FACTOR + 1
     nsnap = N_COARSE_STEPS // EVERY
     buf = torch.empty((N_FINE + 1, N_FINE + 1), dtype=torch.complex64, device="cuda")
@@ -168,6 +176,7 @@ def plain_run(seed, n, prec="f32", noise=1e-3):
         psi_n = psi_n.astype(np.complex64)
     s = _solver(n, V_n, prec)
     s.set_field(psi_n)
+    _tuned(s)
     if n == N_FINE // FACTOR:
         nsteps, dt = N_COARSE_STEPS, DT_C
     else:
@@ -192,6 +201,7 @@ def learned_run(seed, params, scale, noise=1e-3):
     Vc = np.ascontiguousarray(V[::FACTOR, ::FACTOR])
     s = _solver(nc, Vc)
     s.set_field(np.ascontiguousarray(psi[::FACTOR, ::FACTOR]).astype(np.complex64))
+    _tuned(s)
     m = N.Corrector(nc + 1, nc + 1, max_batch=1, V=Vc)
     m.set_params(params, scale)
     torch.cuda.synchronize()
