@@ -41,6 +41,7 @@ WHOLE_STEP_BYTES = {"f64": 40, "f32": 20, "mixed": 36}
 # differences, step 2 and F, plus 26 for the K_tot and Psi updates
 FLOPS_PER_POINT_STEP = 190
 VECTOR_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "mixed": 157.3}
+
 METRIC = "2SHOC-RK4 Gpt·steps/s + % HBM peak; coarse+learned vs plain fine at equal L2 err"
 
 
@@ -57,6 +58,19 @@ def measured_traffic(kind, prec, variant):
     if not ent or ent.get("variant") != variant:
         return None
     return ent["bytes"]
+
+
+def measured_valu_issue(prec, variant):
+    """VALU issue fraction of the whole-step kernel from the committed counter run, if it was taken
+    on this variant and the kernel's sources have not changed since."""
+    try:
+        t = json.load(open(bench_traffic.valu_file()))
+    except (OSError, ValueError):
+        return None
+    ent = t.get("per_launch", {}).get(prec)
+    if t.get("source_sha") != bench_traffic.source_sha("step2d") or not ent or ent.get("variant") != variant:
+        return None
+    return ent["valu_issue"]
 
 
 def parse_variants(spec):
@@ -276,7 +290,12 @@ def main():
                     "frac": achieved / VECTOR_PEAK_TFLOPS[prec], "traffic": measured_traffic("step2d", prec, variant),
                     "kernel": "nlse::step2d_kernel", "algorithmic_flops_per_launch": flops,
                     "algorithmic_bytes_per_launch": bytes_, "hbm_gbs_algorithmic": bytes_ / avg_launch_s / 1e9,
+                    "hbm_frac_algorithmic": bytes_ / avg_launch_s / 1e9 / HBM_PEAK_GBS,
+                    "valu_issue_measured": measured_valu_issue(prec, variant),
+                    "stage_equivalent_gbs": BYTES_PER_POINT_STEP[prec] * npts / avg_launch_s / 1e9,
                     "avg_launch_us": avg_launch_s * 1e6, "tile_variant": variant}
+            if prec != "f64":
+                roof["attainable_peak_without_packed_fp32"] = VECTOR_PEAK_TFLOPS["f64"]
             note = (f"{achieved:.2f} TFLOP/s algorithmic ({100 * roof['frac']:.1f}% of the {prec} vector peak), "
                     f"{roof['hbm_gbs_algorithmic']:.0f} GB/s of HBM")
         else:

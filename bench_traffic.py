@@ -1,6 +1,7 @@
 """Turn two rocprofv3 counter runs of bench.py into per-launch HBM traffic of a 2D kernel.
 
 Usage: python bench_traffic.py <step2d|stage2d> <variant2d> <stage_variant> <fetch_collection.csv> <write_collection.csv>
+       python bench_traffic.py valu <variant2d> <valu_counter_collection.csv>   (VALU issue of the whole-step kernel)
 
 <variant2d> and <stage_variant> are the per-precision kernel variants the counter runs of bench.py
 were given (--variant2d, --stage-variant), e.g. f64:6,f32:3,mixed:3.
@@ -81,5 +82,41 @@ def main(kind, variant2d, stage_variant, fetch_csv, write_csv):
     print(json.dumps(out, indent=1))
 
 
+def valu_file():
+    return os.path.join(ROOT, "profiles", "valu_step2d_gp2d_2048.json")
+
+
+def valu(variant2d, csv_path, simds=1024, xcds=8):
+    """VALU issue of the whole-step kernel from one counter run (SQ_INSTS_VALU, SQ_INSTS_SALU,
+    SQ_INSTS_VALU_FLOPS_FP64/FP32, SQ_WAVES, GRBM_GUI_ACTIVE): issue = SQ_INSTS_VALU x 4 cycles
+    (a wave64 instruction on a 16-lane SIMD) / (SIMDs x GRBM_GUI_ACTIVE per XCD)."""
+    var = {k: int(v) for k, v in (item.split(":") for item in variant2d.split(","))}
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(csv_path)):
+        agg[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    res = {}
+    for prec, keys in KEYS["step2d"].items():
+        names = [k for k in agg for key in keys if key in k]
+        if not names:
+            continue
+        c = {n: sum(v) / len(v) for n, v in agg[names[0]].items()}
+        cycles = c["GRBM_GUI_ACTIVE"] / xcds
+        res[prec] = {"variant": var.get(prec), "valu_issue": c["SQ_INSTS_VALU"] * 4 / (simds * cycles),
+                     "insts_valu": c["SQ_INSTS_VALU"], "insts_salu": c["SQ_INSTS_SALU"], "waves": c["SQ_WAVES"],
+                     "cycles_per_xcd": cycles,
+                     "executed_flops": 64 * (c["SQ_INSTS_VALU_FLOPS_FP64"] + c["SQ_INSTS_VALU_FLOPS_FP32"])}
+    out = {"kernel": NAMES["step2d"], "source_sha": source_sha("step2d"), "per_launch": res,
+           "command": "cd /tmp && rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_VALU_FLOPS_FP64 "
+                      "SQ_INSTS_VALU_FLOPS_FP32 SQ_ACTIVE_INST_VALU SQ_BUSY_CU_CYCLES SQ_WAVES GRBM_GUI_ACTIVE "
+                      "-d $R/gpurun_out/prof_valu -o pmc --output-format csv -- python3 $R/bench.py --steps 5 "
+                      "--warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned "
+                      f"--variant2d {variant2d}"}
+    json.dump(out, open(valu_file(), "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
 if __name__ == "__main__":
-    main(*sys.argv[1:6])
+    if sys.argv[1] == "valu":
+        valu(sys.argv[2], sys.argv[3])
+    else:
+        main(*sys.argv[1:6])
