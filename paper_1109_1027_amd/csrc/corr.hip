@@ -49,10 +49,14 @@ __device__ __forceinline__ unsigned short f2bf(float f)
 }
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
 
-__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + expf(-z)); }
+// SiLU and its derivative through the hardware exponential and reciprocal (about 1 ulp
+// each, far below the bf16 rounding of every activation); training and inference use the
+// same functions, so their forward passes agree bit for bit.
+__device__ __forceinline__ float sigmoid_f(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_f(float z) { return z * sigmoid_f(z); }
 __device__ __forceinline__ float dsilu_f(float z)
 {
-    const float s = 1.0f / (1.0f + expf(-z));
+    const float s = sigmoid_f(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -78,6 +82,23 @@ __device__ __forceinline__ float gauss(uint64_t seed, uint64_t node, int part)
     return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
 }
 
+// The 8 input channels of node (y, x), packed as bf16: Re, Im, 16 h^2 Lap (Re, Im) with the
+// 5-point Laplacian, |Psi|^2, V/4, 0, 0.  at(yy, xx) returns the field (zero outside it).
+template <typename At>
+__device__ __forceinline__ uint4 feat8(const At &at, int y, int x, float v)
+{
+    const float2 u = at(y, x);
+    const float2 n = at(y - 1, x), s = at(y + 1, x), w = at(y, x - 1), e = at(y, x + 1);
+    const float lr = (((n.x + s.x) + w.x) + e.x) - 4.0f * u.x;
+    const float li = (((n.y + s.y) + w.y) + e.y) - 4.0f * u.y;
+    uint4 pk;
+    pk.x = f2bf(u.x) | ((unsigned)f2bf(u.y) << 16);
+    pk.y = f2bf(LAP_SCALE * lr) | ((unsigned)f2bf(LAP_SCALE * li) << 16);
+    pk.z = f2bf(u.x * u.x + u.y * u.y) | ((unsigned)f2bf(V_SCALE * v) << 16);
+    pk.w = 0;
+    return pk;
+}
+
 // X0[p][0..7] for every node of B dense complex fields [B][H][W] (complex64) or of a
 // context's padded master field (templated on the master type).  aug_sigma > 0 adds
 // the augmentation noise to the field before the features are formed.
@@ -101,25 +122,7 @@ __global__ void features_kernel(const C<M> *psi, int64_t pitch_row, int64_t pitc
             }
             return r;
         };
-        const float2 u = at(y, x);
-        const float2 n = at(y - 1, x), s = at(y + 1, x), w = at(y, x - 1), e = at(y, x + 1);
-        const float lr = (((n.x + s.x) + w.x) + e.x) - 4.0f * u.x;
-        const float li = (((n.y + s.y) + w.y) + e.y) - 4.0f * u.y;
-        unsigned short o[8];
-        o[0] = f2bf(u.x);
-        o[1] = f2bf(u.y);
-        o[2] = f2bf(LAP_SCALE * lr);
-        o[3] = f2bf(LAP_SCALE * li);
-        o[4] = f2bf(u.x * u.x + u.y * u.y);
-        o[5] = f2bf(V_SCALE * V[(int64_t)y * W + x]);
-        o[6] = 0;
-        o[7] = 0;
-        uint4 pk;
-        pk.x = o[0] | ((unsigned)o[1] << 16);
-        pk.y = o[2] | ((unsigned)o[3] << 16);
-        pk.z = o[4] | ((unsigned)o[5] << 16);
-        pk.w = 0;
-        reinterpret_cast<uint4 *>(X0)[p] = pk;
+        reinterpret_cast<uint4 *>(X0)[p] = feat8(at, y, x, V[(int64_t)y * W + x]);
     }
 }
 
@@ -176,6 +179,146 @@ __global__ __launch_bounds__(256) void conv_kernel(const unsigned short *X, cons
             if (n < CORR_OUT) Yout[p * CORR_OUT + n] = acc[i] + bias[n];
         } else {
             Aout[p * 32 + n] = f2bf(acc[i] * dsilu_f(Zprev[p * 32 + n]));
+        }
+    }
+}
+
+// ---------------------------------------------------- inference (tiled) --
+// The forward pass without the training outputs, three launches per application:
+//   layer 1: features of Psi (computed into LDS) -> A1,   layer 2: A1 -> A2,
+//   layer 3: A2 -> Y, written out (inference) or added to the interior of Psi (apply).
+// A block of 4 waves owns an output tile of 8 rows x 32 pixels; its 10 x 34-pixel input
+// tile (zero outside the field) is staged in LDS once and every wave reads its 9 taps
+// from there; the packed weights sit in registers.  Each wave computes 2 rows, the
+// reduction over K in the same chunk order with the same operands as conv_kernel, so the
+// results are bit-identical to the training forward pass.
+constexpr int IT_R = 8, IT_W = 32, IT_IR = IT_R + 2, IT_IW = IT_W + 2, IT_PIX = IT_IR * IT_IW;
+
+struct InfArgs {
+    const void *psi;          // layer 1: the field (master of a context, or dense complex64 batch)
+    int64_t pitch_row, pitch_field, off;
+    const float *V;           // dense [H][W]
+    int B, H, W;
+    const unsigned short *X;  // layers 2, 3: input activations [P][32] bf16
+    const bf16x8 *Bpk;        // packed weights of the layer
+    const float *bias;
+    unsigned short *Aout;     // layers 1, 2
+    float *Yout;              // layer 3 (inference) or nullptr
+    void *psi_out;            // layer 3 (apply): the context's master, or nullptr
+    float scale;
+};
+
+template <int L, typename M>
+__global__ __launch_bounds__(256) void infer_kernel(InfArgs A)
+{
+    constexpr int CI = L == 1 ? CORR_CIN : 32;
+    constexpr int SP = CI + 8;                  // LDS pixel stride in bf16 (16-byte pad against bank conflicts)
+    constexpr int NCH = (9 * CI + 15) / 16;
+    __shared__ __attribute__((aligned(16))) unsigned short tile[IT_PIX * SP];
+    __shared__ float ybuf[IT_R][IT_W][2];
+    // per-wave staging of its two output rows as bf16 [row][pixel][channel] (+8 pad), so
+    // that every lane stores 16 contiguous bytes
+    __shared__ __attribute__((aligned(16))) unsigned short obuf[L < 3 ? 4 : 1][2][IT_W][40];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tiles_x = (A.W + IT_W - 1) / IT_W, tiles_y = (A.H + IT_R - 1) / IT_R;
+    const int bx = blockIdx.x % tiles_x, by = (blockIdx.x / tiles_x) % tiles_y, b = blockIdx.x / (tiles_x * tiles_y);
+    const int x0 = bx * IT_W, y0 = by * IT_R;
+    const int64_t fbase = (int64_t)b * A.H * A.W;   // pixel index of this field's (0, 0)
+
+    bf16x8 breg[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) breg[c] = A.Bpk[c * 64 + lane];
+
+    // stage the input tile: pixel (ty, tx) is field node (y0 - 1 + ty, x0 - 1 + tx)
+    if (L == 1) {
+        const C<M> *f = (const C<M> *)A.psi + b * A.pitch_field + A.off;
+        auto at = [&](int yy, int xx) -> float2 {
+            if (yy < 0 || yy >= A.H || xx < 0 || xx >= A.W) return make_float2(0.f, 0.f);
+            const C<M> v = f[(int64_t)yy * A.pitch_row + xx];
+            return make_float2((float)v.x, (float)v.y);
+        };
+        for (int e = threadIdx.x; e < IT_PIX; e += blockDim.x) {
+            const int yy = y0 - 1 + e / IT_IW, xx = x0 - 1 + e % IT_IW;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (yy >= 0 && yy < A.H && xx >= 0 && xx < A.W) v = feat8(at, yy, xx, A.V[(int64_t)yy * A.W + xx]);
+            *reinterpret_cast<uint4 *>(tile + e * SP) = v;
+        }
+    } else {
+        for (int e = threadIdx.x; e < IT_PIX * 4; e += blockDim.x) {
+            const int px = e >> 2, part = e & 3;
+            const int yy = y0 - 1 + px / IT_IW, xx = x0 - 1 + px % IT_IW;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (yy >= 0 && yy < A.H && xx >= 0 && xx < A.W)
+                v = *reinterpret_cast<const uint4 *>(A.X + (fbase + (int64_t)yy * A.W + xx) * 32 + part * 8);
+            *reinterpret_cast<uint4 *>(tile + px * SP + part * 8) = v;
+        }
+    }
+    __syncthreads();
+
+    const int m = lane & 31, half = lane >> 5;
+    f32x16 acc[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[r][i] = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int k0 = 16 * c + 8 * half;
+        const int t = k0 / CI, cb = k0 % CI;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int ty = 2 * wv + r;              // output row within the tile
+            uint4 a = make_uint4(0, 0, 0, 0);
+            if (t < 9) a = *reinterpret_cast<const uint4 *>(tile + ((ty + 1 + tap_dy(t)) * IT_IW + (m + 1 + tap_dx(t))) * SP + cb);
+            acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), breg[c], acc[r], 0, 0, 0);
+        }
+    }
+
+    // accumulator i of lane l holds pixel 8(i/4) + 4(l/32) + i%4, channel l%32
+    const int n = lane & 31;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int ty = 2 * wv + r, y = y0 + ty;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int mm = 8 * (i / 4) + 4 * half + (i % 4);
+            const int xo = x0 + mm;
+            if (L < 3) {
+                obuf[L < 3 ? wv : 0][r][mm][n] = f2bf(silu_f(acc[r][i] + A.bias[n]));
+            } else if (n < CORR_OUT) {
+                ybuf[ty][mm][n] = acc[r][i] + A.bias[n];
+            }
+        }
+    }
+    if (L < 3) {
+        __builtin_amdgcn_wave_barrier();   // the wave reads back only what it wrote
+        // 2 rows x 32 pixels x 64 B = 256 16-byte pieces, 4 per lane
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = q * 64 + lane, r = e >> 7, px = (e >> 2) & 31, part = e & 3;
+            const int y = y0 + 2 * wv + r, xo = x0 + px;
+            if (y < A.H && xo < A.W)
+                *reinterpret_cast<uint4 *>(A.Aout + (fbase + (int64_t)y * A.W + xo) * 32 + part * 8) =
+                    *reinterpret_cast<const uint4 *>(&obuf[L < 3 ? wv : 0][r][px][part * 8]);
+        }
+    }
+    if (L == 3) {
+        __syncthreads();
+        const int ty = threadIdx.x / IT_W, tx = threadIdx.x % IT_W;   // 256 threads = 8 x 32 pixels
+        const int y = y0 + ty, x = x0 + tx;
+        if (y < A.H && x < A.W) {
+            const float y0v = ybuf[ty][tx][0], y1v = ybuf[ty][tx][1];
+            if (A.Yout) {
+                float *o = A.Yout + (fbase + (int64_t)y * A.W + x) * 2;
+                o[0] = y0v;
+                o[1] = y1v;
+            } else if (x > 0 && x < A.W - 1 && y > 0 && y < A.H - 1) {
+                C<M> *q = (C<M> *)A.psi_out + A.off + (int64_t)y * A.pitch_row + x;
+                C<M> v = *q;
+                v.x += (M)(A.scale * y0v);
+                v.y += (M)(A.scale * y1v);
+                *q = v;
+            }
         }
     }
 }
@@ -377,21 +520,6 @@ __global__ void adam_kernel(float *w, const float *g, float *m, float *v, int n,
 }
 
 // Psi <- Psi + scale (Y0 + i Y1) on the interior of a context's padded master field
-template <typename M>
-__global__ void apply_kernel(C<M> *psi, int64_t pitch_row, int64_t off, int H, int W, const float *Y, float scale)
-{
-    const int64_t P = (int64_t)H * W;
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(p % W), y = (int)(p / W);
-        if (x == 0 || x == W - 1 || y == 0 || y == H - 1) continue;
-        C<M> *q = psi + off + (int64_t)y * pitch_row + x;
-        C<M> v = *q;
-        v.x += (M)(scale * Y[p * 2]);
-        v.y += (M)(scale * Y[p * 2 + 1]);
-        *q = v;
-    }
-}
-
 // injection restriction: dst[y][x] = src[f y][f x] (dense complex fields)
 template <typename S, typename D>
 __global__ void inject_kernel(const C<S> *src, int64_t src_w, C<D> *dst, int64_t dst_h, int64_t dst_w, int factor)
@@ -464,6 +592,54 @@ int forward(nlse_corr *m, int B)
     hipLaunchKernelGGL((conv_kernel<32, 1>), dim3(g), dim3(256), 0, m->stream, m->A2, (const bf16x8 *)m->pk3,
                        m->params + OFF_B3, B, m->H, m->W, nullptr, nullptr, nullptr, m->Y, 1);
     HIPTRY(hipGetLastError());
+    return NLSE_OK;
+}
+
+template <int L, typename M>
+hipError_t launch_infer(const InfArgs &a, hipStream_t st)
+{
+    const int tiles = a.B * ((a.H + IT_R - 1) / IT_R) * ((a.W + IT_W - 1) / IT_W);
+    hipLaunchKernelGGL((infer_kernel<L, M>), dim3(tiles), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// Inference of B fields straight from Psi (master type M at psi + off, rows pitch_row apart,
+// fields pitch_field apart): Y to Yout, or (Yout = nullptr) Psi += scale Y on the interior.
+template <typename M>
+int infer_tiled(nlse_corr *m, const void *psi, int64_t pitch_row, int64_t pitch_field, int64_t off, int B,
+                float *Yout, void *psi_out)
+{
+    if (!m->packed) {
+        int rc = pack_all(m);
+        if (rc) return rc;
+    }
+    InfArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.psi = psi;
+    a.pitch_row = pitch_row;
+    a.pitch_field = pitch_field;
+    a.off = off;
+    a.V = m->V;
+    a.B = B;
+    a.H = m->H;
+    a.W = m->W;
+    a.Bpk = (const bf16x8 *)m->pk1;
+    a.bias = m->params + OFF_B1;
+    a.Aout = m->A1;
+    HIPTRY((launch_infer<1, M>(a, m->stream)));
+    a.X = m->A1;
+    a.Bpk = (const bf16x8 *)m->pk2;
+    a.bias = m->params + OFF_B2;
+    a.Aout = m->A2;
+    HIPTRY((launch_infer<2, M>(a, m->stream)));
+    a.X = m->A2;
+    a.Bpk = (const bf16x8 *)m->pk3;
+    a.bias = m->params + OFF_B3;
+    a.Aout = nullptr;
+    a.Yout = Yout;
+    a.psi_out = psi_out;
+    a.scale = (float)m->scale;
+    HIPTRY((launch_infer<3, M>(a, m->stream)));
     return NLSE_OK;
 }
 
@@ -625,11 +801,7 @@ int nlse_corr_get_params(nlse_corr *m, float *params)
 int nlse_corr_infer(nlse_corr *m, const void *psi, int32_t batch, float *y_out)
 {
     if (!m || !psi || !y_out || batch < 1 || batch > m->maxB) return fail(NLSE_E_INVAL, "nlse_corr_infer: bad arguments");
-    int rc = features_dense(m, psi, batch);
-    if (!rc) rc = forward(m, batch);
-    if (rc) return rc;
-    HIPTRY(hipMemcpyAsync(y_out, m->Y, (size_t)batch * m->H * m->W * 8, hipMemcpyDeviceToDevice, m->stream));
-    return NLSE_OK;
+    return infer_tiled<float>(m, psi, m->W, (int64_t)m->H * m->W, 0, batch, y_out, nullptr);
 }
 
 int nlse_corr_grads(nlse_corr *m, const void *pred, const void *ref, int32_t batch, float *grads, double *loss)
@@ -665,25 +837,10 @@ int nlse_corr_apply(nlse_corr *m, nlse_ctx *c)
     if (c->p.ndim != 2 || c->L.nx + 1 != m->W || c->L.ny + 1 != m->H)
         return fail(NLSE_E_INVAL, "nlse_corr_apply: context grid does not match the corrector");
     if (c->stream != m->stream) return fail(NLSE_E_INVAL, "nlse_corr_apply: corrector and context streams differ");
-    const int64_t P = (int64_t)m->H * m->W;
-    const unsigned g = (unsigned)std::min<int64_t>((P + 255) / 256, 65535);
     const int64_t pitch = c->L.px, off = c->L.ox;
-    if (c->esM == 16)
-        hipLaunchKernelGGL((features_kernel<double>), dim3(g), dim3(256), 0, m->stream, (const C<double> *)c->psi,
-                           pitch, (int64_t)0, off, m->V, 1, m->H, m->W, m->X0, 0.f, (uint64_t)0);
-    else
-        hipLaunchKernelGGL((features_kernel<float>), dim3(g), dim3(256), 0, m->stream, (const C<float> *)c->psi,
-                           pitch, (int64_t)0, off, m->V, 1, m->H, m->W, m->X0, 0.f, (uint64_t)0);
-    HIPTRY(hipGetLastError());
-    int rc = forward(m, 1);
+    const int rc = c->esM == 16 ? infer_tiled<double>(m, c->psi, pitch, 0, off, 1, nullptr, c->psi)
+                                : infer_tiled<float>(m, c->psi, pitch, 0, off, 1, nullptr, c->psi);
     if (rc) return rc;
-    if (c->esM == 16)
-        hipLaunchKernelGGL((apply_kernel<double>), dim3(g), dim3(256), 0, m->stream, (C<double> *)c->psi, pitch, off,
-                           m->H, m->W, m->Y, (float)m->scale);
-    else
-        hipLaunchKernelGGL((apply_kernel<float>), dim3(g), dim3(256), 0, m->stream, (C<float> *)c->psi, pitch, off,
-                           m->H, m->W, m->Y, (float)m->scale);
-    HIPTRY(hipGetLastError());
     // stage fields hold the master's boundary values only; their interiors are rewritten by the next step
     return NLSE_OK;
 }
