@@ -67,13 +67,15 @@ hipError_t launch_v(const Step2DArgs &a, hipStream_t st)
     case 1: return launch_q<R, M, 4>(a, st);    // 20
     case 2: return launch_q<R, M, 6>(a, st);    // 38
     case 3: return launch_q<R, M, 8>(a, st);    // 56
+    case 4: return launch_q<R, M, 3>(a, st);    // 11 (small grids: more, shorter waves)
+    case 5: return launch_q<R, M, 7>(a, st);    // 47
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-int step2d_variants() { return 4; }
+int step2d_variants() { return 6; }
 
 hipError_t launch_step2d(Prec prec, const Step2DArgs &a, hipStream_t st)
 {
