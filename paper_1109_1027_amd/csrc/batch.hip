@@ -1,18 +1,21 @@
 // Batched 2SHOC-RK4: thousands of independent 1D and 2D problems of uneven size
-// advanced by one persistent kernel, captured once in a hipGraph.
+// advanced by one graph launch: a queue reset and two persistent kernels, captured
+// once in a hipGraph.
 //
 // Each instance is an ordinary context (its own padded arrays, boundary closure,
-// step-size bound); the batch adds a device table of instances, a work queue
-// and the graph.  Workgroups of the persistent kernel pop instance indices from
-// the queue in longest-first order and advance the popped instance through all
+// step-size bound); the batch adds a device table of instances, two work queues
+// and the graph.  Workgroups of each persistent kernel pop instance indices from
+// their queue (longest first) and advance the popped instance through all
 // requested steps before popping again:
-//   - a 1D instance runs entirely on chip (onchip1d.h): HBM is touched twice;
-//   - a 2D instance advances by whole RK4 steps (wave2d.h): the waves of the
-//     workgroup share out its (strip, row segment) tasks, reading Psi^n and V
-//     and writing Psi^{n+1} into the instance's second master buffer, with one
-//     workgroup barrier per step; an odd step count ends with a copy back.
-// Every workgroup leaves the loop when the queue is exhausted, so the grid
-// always drains.  Instances never share memory, so no cross-workgroup
+//   - 2D kernel: an instance advances by whole RK4 steps (wave2d.h); the waves of
+//     the workgroup (16 in FP32, where the body fits 128 VGPRs, else 8) share out
+//     its (strip, row segment) tasks, reading Psi^n and V and writing Psi^{n+1}
+//     into the instance's second master buffer, one workgroup barrier per step; an
+//     odd step count ends with a copy back;
+//   - 1D kernel: an instance runs entirely on chip (onchip1d.h): HBM is touched
+//     twice.
+// Every workgroup leaves its loop when its queue is exhausted, so both grids
+// always drain.  Instances never share memory, so no cross-workgroup
 // synchronisation exists.
 #include <algorithm>
 #include <cmath>
@@ -38,128 +41,153 @@ struct BatchItem {
     int msd;
 };
 
-constexpr int BATCH_BS = 512;
-constexpr int BATCH_NW = BATCH_BS / 64;
+constexpr int BATCH_BS = 512;       // 1D workgroups
 
 template <typename R> struct BatchNPT;
 template <> struct BatchNPT<double> { static constexpr int v = 10; };
 template <> struct BatchNPT<float> { static constexpr int v = 17; };
 
+// 2D workgroups: 16 waves where the whole-step body fits 128 VGPRs (FP32: four waves per
+// SIMD), 8 waves otherwise.
+template <typename R, typename M> struct Batch2DWaves { static constexpr int v = 8; };
+template <> struct Batch2DWaves<float, float> { static constexpr int v = 16; };
+
 __global__ void batch_reset_kernel(int *queue)
 {
-    if (threadIdx.x == 0) queue[0] = 0;
+    if (threadIdx.x < 2) queue[threadIdx.x] = 0;
 }
 
-template <typename R, typename M, int Q>
-__global__ __launch_bounds__(BATCH_BS) void batch_kernel(const BatchItem *items, const int *order, int count,
-                                                         int *queue, int64_t nsteps)
+// Persistent kernel for the 2D instances (order[0 .. n2d)).
+template <typename R, typename M, int Q, int NW>
+__global__ __launch_bounds__(64 * NW) void batch2d_kernel(const BatchItem *items, const int *order, int n2d,
+                                                          int *queue, int64_t nsteps)
 {
     extern __shared__ unsigned char smem[];
     __shared__ int s_item;
-    constexpr int NPT = BatchNPT<R>::v;
     constexpr int FR = wave2d::face_rows<Q>();
+    auto *sdx = reinterpret_cast<C<R>(*)[2][FR]>(smem);                  // [NW][2][FR]
+    auto *sdy = reinterpret_cast<C<R>(*)[2][64]>(smem + sizeof(C<R>) * NW * 2 * FR);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
         __syncthreads();
         const int it = s_item;
-        if (it >= count) break;   // workgroup-uniform: the queue is exhausted
+        if (it >= n2d) break;   // workgroup-uniform: the queue is exhausted
         const BatchItem &I = items[order[it]];
         const double dt = I.dt;
-        if (I.L.dim == 1) {
-            Solve1DArgs a;
-            a.psin = I.psi;
-            a.V = I.V;
-            a.L = I.L;
-            a.c = I.c;
-            a.k = dt;
-            a.k2 = dt / 2.0;
-            a.k6 = dt / 6.0;
-            a.nsteps = nsteps;
-            a.msd = I.msd;
-            solve1d_onchip<R, M, BATCH_BS, NPT>(a, smem);
-        } else {
-            auto *sdx = reinterpret_cast<C<R>(*)[2][FR]>(smem);                  // [BATCH_NW][2][FR]
-            auto *sdy = reinterpret_cast<C<R>(*)[2][64]>(smem + sizeof(C<R>) * BATCH_NW * 2 * FR);
-            const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-            const int strips = wave2d::strips(I.L.nx);
-            const int tasks = strips * wave2d::segments<Q>(I.L.ny);
-            Step2DArgs a;
-            a.V = I.V;
-            a.DB[0] = I.DB[0];
-            a.DB[1] = I.DB[1];
-            a.L = I.L;
-            a.c = I.c;
-            a.ck[0] = dt / 2.0;
-            a.ck[1] = dt / 2.0;
-            a.ck[2] = dt;
-            a.ck[3] = dt / 6.0;
-            a.variant = 0;
-            void *cur = I.psi, *nxt = I.psi2;
-            for (int64_t step = 0; step < nsteps; ++step) {
-                a.psi_in = cur;
-                a.psi_out = nxt;
-                for (int task = wv; task < tasks; task += BATCH_NW)
-                    wave2d::step2d_wave<R, M, Q>(a, task % strips, task / strips, threadIdx.x & 63, sdx[wv], sdy[wv]);
-                __syncthreads();   // Psi^{n+1} complete before any task reads it
-                void *t = cur;
-                cur = nxt;
-                nxt = t;
-            }
-            if (cur != I.psi) {    // odd step count: the result is in psi2
-                const C<M> *src = (const C<M> *)cur;
-                C<M> *dst = (C<M> *)I.psi;
-                for (int64_t e = threadIdx.x; e < I.L.total; e += BATCH_BS) dst[e] = src[e];
-            }
+        const int strips = wave2d::strips(I.L.nx);
+        const int tasks = strips * wave2d::segments<Q>(I.L.ny);
+        Step2DArgs a;
+        a.V = I.V;
+        a.DB[0] = I.DB[0];
+        a.DB[1] = I.DB[1];
+        a.L = I.L;
+        a.c = I.c;
+        a.ck[0] = dt / 2.0;
+        a.ck[1] = dt / 2.0;
+        a.ck[2] = dt;
+        a.ck[3] = dt / 6.0;
+        a.variant = 0;
+        void *cur = I.psi, *nxt = I.psi2;
+        for (int64_t step = 0; step < nsteps; ++step) {
+            a.psi_in = cur;
+            a.psi_out = nxt;
+            for (int task = wv; task < tasks; task += NW)
+                wave2d::step2d_wave<R, M, Q>(a, task % strips, task / strips, threadIdx.x & 63, sdx[wv], sdy[wv]);
+            __syncthreads();   // Psi^{n+1} complete before any task reads it
+            void *t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        if (cur != I.psi) {    // odd step count: the result is in psi2
+            const C<M> *src = (const C<M> *)cur;
+            C<M> *dst = (C<M> *)I.psi;
+            for (int64_t e = threadIdx.x; e < I.L.total; e += 64 * NW) dst[e] = src[e];
         }
     }
 }
 
-template <typename R, int Q>
-static size_t batch_lds(int64_t max1d_nodes, bool has2d)
+// Persistent kernel for the 1D instances (order[n2d .. n2d + n1d)).
+template <typename R, typename M>
+__global__ __launch_bounds__(BATCH_BS) void batch1d_kernel(const BatchItem *items, const int *order, int n1d,
+                                                           int *queue, int64_t nsteps)
 {
-    const size_t l1 = max1d_nodes > 0 ? onchip1d_lds<R, BATCH_BS>() : 0;
-    const size_t l2 = has2d ? sizeof(C<R>) * BATCH_NW * 2 * (wave2d::face_rows<Q>() + 64) : 0;
-    return std::max(l1, l2);
+    extern __shared__ unsigned char smem[];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= n1d) break;
+        const BatchItem &I = items[order[it]];
+        Solve1DArgs a;
+        a.psin = I.psi;
+        a.V = I.V;
+        a.L = I.L;
+        a.c = I.c;
+        a.k = I.dt;
+        a.k2 = I.dt / 2.0;
+        a.k6 = I.dt / 6.0;
+        a.nsteps = nsteps;
+        a.msd = I.msd;
+        solve1d_onchip<R, M, BATCH_BS, BatchNPT<R>::v>(a, smem);
+    }
 }
+
+// Variant v selects the row-segment length of the 2D whole-step tasks: 56, 29 or 20 rows.
+constexpr int BATCH_VARIANTS = 3;
+
+struct BatchLaunch {
+    const BatchItem *items;
+    const int *order;        // the n2d 2D instances, then the n1d 1D instances (longest first)
+    int n2d, n1d;
+    int *queue;              // [2]: next 2D, next 1D
+    int64_t nsteps;
+    int grid2d, grid1d;
+};
 
 template <typename R, typename M, int Q>
-static hipError_t launch_batch_q(const BatchItem *items, const int *order, int count, int *queue, int64_t nsteps,
-                                 int grid, size_t lds, hipStream_t st)
+static hipError_t launch_batch_q(const BatchLaunch &L, hipStream_t st)
 {
-    (void)hipFuncSetAttribute((const void *)batch_kernel<R, M, Q>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, queue);
+    constexpr int NW = Batch2DWaves<R, M>::v;
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, L.queue);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((batch_kernel<R, M, Q>), dim3(grid), dim3(BATCH_BS), lds, st, items, order, count, queue,
-                       nsteps);
-    return hipGetLastError();
+    if (L.n2d > 0) {
+        const size_t lds = sizeof(C<R>) * NW * 2 * (wave2d::face_rows<Q>() + 64);
+        hipLaunchKernelGGL((batch2d_kernel<R, M, Q, NW>), dim3(L.grid2d), dim3(64 * NW), lds, st, L.items, L.order,
+                           L.n2d, L.queue, L.nsteps);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (L.n1d > 0) {
+        const size_t lds1 = onchip1d_lds<R, BATCH_BS>();
+        hipLaunchKernelGGL((batch1d_kernel<R, M>), dim3(L.grid1d), dim3(BATCH_BS), lds1, st, L.items, L.order + L.n2d,
+                           L.n1d, L.queue + 1, L.nsteps);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
-// Variant v selects the row-segment length of the 2D whole-step tasks: 56 rows
-// (v = 0) or 29 rows (v = 1).
-constexpr int BATCH_VARIANTS = 2;
-
-static size_t batch_lds_for(Prec prec, int variant, int64_t max1d, bool has2d)
+template <typename R, typename M>
+static hipError_t launch_batch_v(int variant, const BatchLaunch &L, hipStream_t st)
 {
-    if (prec == P_F64) return variant == 0 ? batch_lds<double, 8>(max1d, has2d) : batch_lds<double, 5>(max1d, has2d);
-    return variant == 0 ? batch_lds<float, 8>(max1d, has2d) : batch_lds<float, 5>(max1d, has2d);
+    switch (variant) {
+    case 0: return launch_batch_q<R, M, 8>(L, st);
+    case 1: return launch_batch_q<R, M, 5>(L, st);
+    case 2: return launch_batch_q<R, M, 4>(L, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
-static hipError_t launch_batch(Prec prec, int variant, const BatchItem *items, const int *order, int count,
-                               int *queue, int64_t nsteps, int grid, size_t lds, hipStream_t st)
+static hipError_t launch_batch(Prec prec, int variant, const BatchLaunch &L, hipStream_t st)
 {
     switch (prec) {
-    case P_F64:
-        return variant == 0 ? launch_batch_q<double, double, 8>(items, order, count, queue, nsteps, grid, lds, st)
-                            : launch_batch_q<double, double, 5>(items, order, count, queue, nsteps, grid, lds, st);
-    case P_F32:
-        return variant == 0 ? launch_batch_q<float, float, 8>(items, order, count, queue, nsteps, grid, lds, st)
-                            : launch_batch_q<float, float, 5>(items, order, count, queue, nsteps, grid, lds, st);
-    default:
-        return variant == 0 ? launch_batch_q<float, double, 8>(items, order, count, queue, nsteps, grid, lds, st)
-                            : launch_batch_q<float, double, 5>(items, order, count, queue, nsteps, grid, lds, st);
+    case P_F64: return launch_batch_v<double, double>(variant, L, st);
+    case P_F32: return launch_batch_v<float, float>(variant, L, st);
+    default: return launch_batch_v<float, double>(variant, L, st);
     }
 }
 
@@ -176,10 +204,8 @@ struct nlse_batch {
     int *d_queue = nullptr;
     bool dirty = true;
     int variant = 0;
-    int grid = 0;
-    size_t lds = 0;
-    int64_t max1d = 0;
-    bool has2d = false;
+    int n2d = 0, n1d = 0;       // instance counts by kind
+    int cus = 256;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t graph_steps = -1;
@@ -217,8 +243,9 @@ static int upload_items(nlse_batch *b)
         it.c = base_coeffs(c->p);
         it.dt = b->dt[i];
         it.msd = c->p.bc == NLSE_BC_MSD;
-        // work estimate for longest-first ordering: 2D instances stream through memory
-        work[i] = c->p.ndim == 1 ? (c->L.nx + 1) : 16 * (c->L.nx + 1) * (c->L.ny + 1);
+        // order: the 2D instances first (their kernel runs first), then the 1D ones, each kind
+        // longest first
+        work[i] = c->p.ndim == 2 ? (int64_t(1) << 40) + (c->L.nx + 1) * (c->L.ny + 1) : (c->L.nx + 1);
     }
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
@@ -265,12 +292,12 @@ int nlse_batch_create(nlse_batch **out, const nlse_params *items, int32_t count)
         }
         b->ctx.push_back(c);
         b->dt.push_back(0.0);
-        if (items[i].ndim == 1) b->max1d = std::max(b->max1d, items[i].n[0] + 1);
-        else b->has2d = true;
+        if (items[i].ndim == 1) ++b->n1d;
+        else ++b->n2d;
     }
     hipError_t e = hipMalloc((void **)&b->d_items, sizeof(BatchItem) * count);
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_order, sizeof(int) * count);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_queue, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_queue, 2 * sizeof(int));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         batch_free(b);
@@ -279,7 +306,7 @@ int nlse_batch_create(nlse_batch **out, const nlse_params *items, int32_t count)
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    b->grid = std::max(1, std::min(count, cus > 0 ? cus : 256));
+    b->cus = cus > 0 ? cus : 256;
     *out = b;
     return NLSE_OK;
 }
@@ -369,10 +396,17 @@ int nlse_batch_step(nlse_batch *b, int64_t nsteps)
         if (b->graph) (void)hipGraphDestroy(b->graph);
         b->exec = nullptr;
         b->graph = nullptr;
-        b->lds = batch_lds_for(b->prec, b->variant, b->max1d, b->has2d);
         HIPTRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
-        hipError_t e = launch_batch(b->prec, b->variant, b->d_items, b->d_order, (int)b->ctx.size(), b->d_queue,
-                                    nsteps, b->grid, b->lds, b->cap);
+        BatchLaunch L;
+        L.items = b->d_items;
+        L.order = b->d_order;
+        L.n2d = b->n2d;
+        L.n1d = b->n1d;
+        L.queue = b->d_queue;
+        L.nsteps = nsteps;
+        L.grid2d = std::max(1, std::min(b->n2d, b->cus));
+        L.grid1d = std::max(1, std::min(b->n1d, b->cus));
+        hipError_t e = launch_batch(b->prec, b->variant, L, b->cap);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(b->cap, &g);
         if (e != hipSuccess) return hipfail(e, "batch kernel capture");

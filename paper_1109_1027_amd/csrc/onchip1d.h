@@ -90,6 +90,13 @@ __device__ void solve1d_onchip(const Solve1DArgs &A, unsigned char *smem_raw)
         D[j] = czero<R>();
     }
 
+    // A wave whose first node lies beyond n owns no node: it only takes part in the two
+    // barriers of every stage (s_barrier counts waves, not code locations).
+    const bool busy = wv * 64 * npt - sh <= n;
+    if (!busy) {
+        for (int64_t b = 0; b < 8 * A.nsteps; ++b) __syncthreads();
+        return;
+    }
     for (int64_t step = 0; step < A.nsteps; ++step) {
 #pragma unroll 1
         for (int st = 0; st < 4; ++st) {

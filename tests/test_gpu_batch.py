@@ -62,7 +62,7 @@ def test_batch_matches_oracle(gpu, orc, prec):
         assert err <= tol, (sp.name, sp.grid.n, err)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_batch_bitwise_equals_single(gpu, variant):
     specs = small_mix(seed=9)
     b = gpu.Batch(specs, prec="f32")
@@ -85,7 +85,7 @@ def test_batch_graph_replay_and_autotune(gpu):
     a.set_fields(specs)
     a.set_dts(0.5)
     v = a.autotune(nsteps=5, force=True)
-    assert v in (0, 1)
+    assert 0 <= v < a.variant_count()
     a.step(10)
     a.step(10)
     c = gpu.Batch(specs, prec="f32")
