@@ -41,11 +41,11 @@ struct BatchItem {
     int msd;
 };
 
-constexpr int BATCH_BS = 512;       // 1D workgroups
-
-template <typename R> struct BatchNPT;
-template <> struct BatchNPT<double> { static constexpr int v = 10; };
-template <> struct BatchNPT<float> { static constexpr int v = 17; };
+// 1D workgroups: threads x nodes per thread.  FP32 fits 9 nodes per thread in 128 VGPRs,
+// so 1024-thread workgroups run four waves per SIMD; the FP64-master types keep 512 threads.
+template <typename R, typename M> struct Batch1D { static constexpr int BS = 512, NPT = 10; };
+template <> struct Batch1D<float, float> { static constexpr int BS = 1024, NPT = 9; };
+template <> struct Batch1D<float, double> { static constexpr int BS = 512, NPT = 17; };
 
 // 2D workgroups: 16 waves where the whole-step body fits 128 VGPRs (FP32: four waves per
 // SIMD), 8 waves otherwise.
@@ -109,8 +109,8 @@ __global__ __launch_bounds__(64 * NW) void batch2d_kernel(const BatchItem *items
 }
 
 // Persistent kernel for the 1D instances (order[n2d .. n2d + n1d)).
-template <typename R, typename M>
-__global__ __launch_bounds__(BATCH_BS) void batch1d_kernel(const BatchItem *items, const int *order, int n1d,
+template <typename R, typename M, int BS, int NPT>
+__global__ __launch_bounds__(BS) void batch1d_kernel(const BatchItem *items, const int *order, int n1d,
                                                            int *queue, int64_t nsteps)
 {
     extern __shared__ unsigned char smem[];
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(BATCH_BS) void batch1d_kernel(const BatchItem *item
         a.k6 = I.dt / 6.0;
         a.nsteps = nsteps;
         a.msd = I.msd;
-        solve1d_onchip<R, M, BATCH_BS, BatchNPT<R>::v>(a, smem);
+        solve1d_onchip<R, M, BS, NPT>(a, smem);
     }
 }
 
@@ -163,9 +163,10 @@ static hipError_t launch_batch_q(const BatchLaunch &L, hipStream_t st)
         if (e != hipSuccess) return e;
     }
     if (L.n1d > 0) {
-        const size_t lds1 = onchip1d_lds<R, BATCH_BS>();
-        hipLaunchKernelGGL((batch1d_kernel<R, M>), dim3(L.grid1d), dim3(BATCH_BS), lds1, st, L.items, L.order + L.n2d,
-                           L.n1d, L.queue + 1, L.nsteps);
+        constexpr int BS = Batch1D<R, M>::BS;
+        const size_t lds1 = onchip1d_lds<R, BS>();
+        hipLaunchKernelGGL((batch1d_kernel<R, M, BS, Batch1D<R, M>::NPT>), dim3(L.grid1d), dim3(BS), lds1, st,
+                           L.items, L.order + L.n2d, L.n1d, L.queue + 1, L.nsteps);
         e = hipGetLastError();
     }
     return e;
@@ -272,8 +273,9 @@ int nlse_batch_create(nlse_batch **out, const nlse_params *items, int32_t count)
     nlse_batch *b = new nlse_batch();
     b->prec = (Prec)items[0].prec;
     b->stream = (hipStream_t)items[0].stream;
-    const int64_t cap1d = b->prec == P_F64 ? (int64_t)BATCH_BS * BatchNPT<double>::v
-                                           : (int64_t)BATCH_BS * BatchNPT<float>::v;
+    const int64_t cap1d = b->prec == P_F64   ? (int64_t)Batch1D<double, double>::BS * Batch1D<double, double>::NPT
+                          : b->prec == P_F32 ? (int64_t)Batch1D<float, float>::BS * Batch1D<float, float>::NPT
+                                             : (int64_t)Batch1D<float, double>::BS * Batch1D<float, double>::NPT;
     for (int i = 0; i < count; ++i) {
         if (items[i].ndim == 1 && items[i].n[0] + 1 > cap1d) {
             batch_free(b);
