@@ -82,11 +82,13 @@ def parse_variants(spec):
     return out
 
 
-def time_solver(P, spec, prec, steps, warmup, variant=None):
+def time_solver(P, spec, prec, steps, warmup, variant=None, stencil=None):
     """Time `steps` RK4 steps after `warmup` untimed ones; HIP events on the solver's stream.
     variant None: the library's autotuner picks the kernel variant (untimed)."""
     import torch
     s = P.Solver.from_spec(spec, prec=prec)
+    if stencil:
+        s.stencil = stencil
     s.set_field(spec.psi0)
     dt = 0.5 * s.max_dt()
     if variant is None:
@@ -257,6 +259,7 @@ def main():
     ap.add_argument("--steps3d", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=1000, help="steps of the batched workload (0: skip)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-corrector comparison")
+    ap.add_argument("--no-stencils", action="store_true", help="skip the 2SHOC / non-compact / CD comparison")
     ap.add_argument("--variant2d", default="", help="force 2D kernel variants per precision, e.g. f64:6,f32:3 "
                                                     "(default: the library's autotuner)")
     ap.add_argument("--stage-variant", default="", help="force the stage-kernel comparison variants, e.g. f64:1")
@@ -325,6 +328,23 @@ def main():
         print(f"[bench] {prec} stage kernels: {res[prec]['stage_kernels']['value']:.2f} Gpt*steps/s, "
               f"{ach_s:.0f} GB/s algorithmic ({100 * ach_s / HBM_PEAK_GBS:.1f}% of HBM peak)",
               file=sys.stderr, flush=True)
+    # Sec. 5's comparison on this hardware: the stage kernels with the 2SHOC, the non-compact
+    # fourth-order and the second-order CD Laplacian (same bytes, different operation counts)
+    stencils = {}
+    if not args.no_stencils:
+        for prec in ("f64", "f32"):
+            if prec not in res:
+                continue
+            sv = res[prec]["stage_kernels"]["roofline"]["tile_variant"]
+            for st in ("2shoc", "noncompact", "cd"):
+                ms_s = time_solver(P, spec, prec, args.steps // 4, 10, variant=sv, stencil=st)[0]
+                steps_s = args.steps // 4
+                bw = BYTES_PER_POINT_STEP[prec] * npts * steps_s / (ms_s * 1e-3) / 1e9
+                stencils.setdefault(prec, {})[st] = {"value": npts * steps_s / (ms_s * 1e-3) / 1e9,
+                                                     "ms_per_step": ms_s / steps_s, "algorithmic_gbs": bw,
+                                                     "hbm_frac": bw / HBM_PEAK_GBS, "tile_variant": sv}
+                print(f"[bench] stencil {st} {prec} (stage kernels): {stencils[prec][st]['value']:.2f} Gpt*steps/s, "
+                      f"{100 * bw / HBM_PEAK_GBS:.1f}% of HBM peak", file=sys.stderr, flush=True)
     main_prec = precs[0]
     out = {
         "metric": METRIC, "value": res[main_prec]["value"], "unit": "Gpt·steps/s", "n_gpus": 1,
@@ -346,6 +366,8 @@ def main():
     except Exception as e:  # context only
         out["copy_ceiling_gbs"] = None
         print(f"[bench] copy ceiling failed: {e}", file=sys.stderr)
+    if stencils:
+        out["stencils_stage_kernels"] = stencils
     if args.n3d > 0:
         out["gp3d"] = bench_3d(P, I, args)
     if args.batch_steps > 0:

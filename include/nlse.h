@@ -67,6 +67,14 @@ typedef enum {
     NLSE_BC_MSD = 1        /* |Psi_b|^2 constant (Eqs. msdbc_ut, msdbc_lap); 1D only */
 } nlse_bc;
 
+typedef enum {
+    NLSE_STENCIL_2SHOC = 0,       /* the two-step compact scheme (Sec. 2), the default */
+    NLSE_STENCIL_NONCOMPACT = 1,  /* non-compact fourth-order stencil per axis, the scheme 2SHOC
+                                     is compared with (Sec. 2.1, Sec. 5); beyond the boundary it
+                                     reads the odd reflection 2 Psi_b - Psi_{b+-1} */
+    NLSE_STENCIL_CD = 2           /* second-order central difference (Sec. 3.1's CD) */
+} nlse_stencil;
+
 typedef struct {
     int32_t ndim;          /* 1, 2 or 3 */
     int64_t n[3];          /* intervals per axis (n[a] >= 2 for a < ndim) */
@@ -143,9 +151,19 @@ int nlse_variant_count(const nlse_ctx *c);
 int nlse_set_variant(nlse_ctx *c, int variant);   /* NLSE_E_INVAL if out of range */
 int nlse_get_variant(const nlse_ctx *c);
 
+/* Laplacian of the right-hand side (2D contexts; NLSE_E_UNSUPPORTED for the
+ * alternatives in 1D / 3D, NLSE_E_INVAL for an unknown value).  The alternatives run
+ * in the stage kernels only, so the whole-step variants disappear from the variant
+ * list while they are selected (a whole-step variant then reverts to variant 0).
+ * nlse_max_dt keeps the 2SHOC bound of Eq. kdfull (the non-compact stencil has the
+ * same spectral radius, CD a smaller one), and nlse_energy always uses the 2SHOC
+ * Laplacian.  For the comparisons of Sec. 5 on this hardware. */
+int nlse_set_stencil(nlse_ctx *c, int32_t stencil);
+int nlse_get_stencil(const nlse_ctx *c);
+
 /* Autotuner: times `reps` RK4 steps of every variant on this context's own arrays
  * (twice, keeping the fastest), selects the fastest and caches the choice for the
- * process under (ndim, precision, n).  Later calls reuse the cached choice unless
+ * process under (ndim, precision, n, stencil).  Later calls reuse the cached choice unless
  * force != 0.  Needs a field (nlse_set_field).  The field is saved to a temporary
  * device buffer first and restored afterwards, so the integration state is unchanged;
  * NLSE_E_NOMEM if that buffer cannot be allocated.  Waits for the stream.  The chosen

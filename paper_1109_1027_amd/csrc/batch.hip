@@ -72,7 +72,7 @@ __global__ __launch_bounds__(64 * NW) void batch2d_kernel(const BatchItem *items
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
         __syncthreads();
-        const int it = s_item;
+        const int it = __builtin_amdgcn_readfirstlane(s_item);   // uniform: item fields go to SGPRs
         if (it >= n2d) break;   // workgroup-uniform: the queue is exhausted
         const BatchItem &I = items[order[it]];
         const double dt = I.dt;
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(BS) void batch1d_kernel(const BatchItem *items, con
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
         __syncthreads();
-        const int it = s_item;
+        const int it = __builtin_amdgcn_readfirstlane(s_item);   // uniform: item fields go to SGPRs
         if (it >= n1d) break;
         const BatchItem &I = items[order[it]];
         Solve1DArgs a;

@@ -25,6 +25,7 @@ struct StageArgs {
     Coeffs c;
     int stage;
     int variant;        // tile-shape variant (see stage2d_variants / stage3d_variants)
+    int stencil;        // 2D: 0 2SHOC, 1 non-compact fourth order, 2 second-order CD
 };
 
 // 2D fused stage kernel: per-axis 2SHOC, one 64-column x RW-row tile per wave.

@@ -32,6 +32,27 @@ __device__ __forceinline__ C<R> lap2(C<R> dx, C<R> dy, C<R> dxl, C<R> dxr, C<R> 
     return mk<R>(fmar(c76, ax, -(c112 * bx)), fmar(c76, ay, -(c112 * by)));
 }
 
+// Non-compact fourth-order second difference along one axis (Sec. 2.1, the stencil the
+// 2SHOC scheme is compared with): (-Psi_{+2} + 16 Psi_{+1} - 30 Psi_0 + 16 Psi_{-1} - Psi_{-2})
+// / (12 h^2), accumulated left to right; i12h2 = 1 / (12 h^2).
+template <typename R>
+__device__ __forceinline__ C<R> d4nc(C<R> m2, C<R> m1, C<R> c, C<R> p1, C<R> p2, R i12h2)
+{
+#pragma clang fp contract(off)
+    const R tx = fmar(R(16), m1.x, fmar(R(-30), c.x, fmar(R(16), p1.x, -p2.x))) - m2.x;
+    const R ty = fmar(R(16), m1.y, fmar(R(-30), c.y, fmar(R(16), p1.y, -p2.y))) - m2.y;
+    return mk<R>(tx * i12h2, ty * i12h2);
+}
+
+// Odd reflection across a boundary node b: the ghost value 2 Psi_b - Psi_{b-+1} that makes
+// the second difference vanish at b (the non-compact stencil's value one node outside).
+template <typename R>
+__device__ __forceinline__ C<R> ghost(C<R> b, C<R> inner)
+{
+#pragma clang fp contract(off)
+    return mk<R>(fmar(R(2), b.x, -inner.x), fmar(R(2), b.y, -inner.y));
+}
+
 // Step 2 of the 1D form (Sec. 2.1, Eq. 2shoc1d2): (7/6) D_i - (1/12)(D_{i+1} + D_{i-1}).
 template <typename R>
 __device__ __forceinline__ C<R> lap1(C<R> d, C<R> dl, C<R> dr, R c76, R c112)

@@ -78,11 +78,14 @@ static void free_ctx(nlse_ctx *c)
 }
 
 // Autotuner results shared by every context of the same shape in the process.
-using TuneKey = std::tuple<int, int, int64_t, int64_t, int64_t>;   // dim, precision, nx, ny, nz
+using TuneKey = std::tuple<int, int, int64_t, int64_t, int64_t, int>;   // dim, precision, nx, ny, nz, stencil
 static std::map<TuneKey, int> g_tuned;
 static std::mutex g_tuned_mu;
 
-static TuneKey tune_key(const nlse_ctx *c) { return TuneKey(c->p.ndim, (int)c->prec, c->L.nx, c->L.ny, c->L.nz); }
+static TuneKey tune_key(const nlse_ctx *c)
+{
+    return TuneKey(c->p.ndim, (int)c->prec, c->L.nx, c->L.ny, c->L.nz, c->stencil);
+}
 
 static hipError_t launch_stage(nlse_ctx *c, int stage, double dt, int variant)
 {
@@ -101,12 +104,16 @@ static hipError_t launch_stage(nlse_ctx *c, int stage, double dt, int variant)
     a.c.ck = ck[stage - 1];
     a.stage = stage;
     a.variant = variant;
+    a.stencil = c->stencil;
     return c->p.ndim == 2 ? launch_stage2d(c->prec, a, c->stream) : launch_stage3d(c->prec, a, c->stream);
 }
 
 // 2D variants: [0, stage2d_variants()) are the stage kernels, the rest the
 // whole-step kernels (their 32-bit offsets need fields below 2^31 elements).
-static bool step2d_ok(const nlse_ctx *c) { return c->p.ndim == 2 && c->L.total < (int64_t(1) << 31); }
+static bool step2d_ok(const nlse_ctx *c)
+{
+    return c->p.ndim == 2 && c->stencil == NLSE_STENCIL_2SHOC && c->L.total < (int64_t(1) << 31);
+}
 
 static int variant_count(const nlse_ctx *c)
 {
@@ -170,6 +177,23 @@ int nlse_get_variant(const nlse_ctx *c)
 {
     if (!c) return fail(NLSE_E_INVAL, "NULL context");
     return c->variant;
+}
+
+int nlse_set_stencil(nlse_ctx *c, int32_t stencil)
+{
+    if (!c) return fail(NLSE_E_INVAL, "NULL context");
+    if (stencil < NLSE_STENCIL_2SHOC || stencil > NLSE_STENCIL_CD) return fail(NLSE_E_INVAL, "unknown stencil");
+    if (stencil != NLSE_STENCIL_2SHOC && c->p.ndim != 2)
+        return fail(NLSE_E_UNSUPPORTED, "the alternative stencils are implemented in 2D only");
+    c->stencil = stencil;
+    if (c->variant >= variant_count(c)) c->variant = 0;   // whole-step variants are 2SHOC only
+    return NLSE_OK;
+}
+
+int nlse_get_stencil(const nlse_ctx *c)
+{
+    if (!c) return fail(NLSE_E_INVAL, "NULL context");
+    return c->stencil;
 }
 
 int nlse_autotune(nlse_ctx *c, int reps, int force, int *chosen)

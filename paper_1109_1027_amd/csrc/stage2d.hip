@@ -23,39 +23,57 @@
 // brings the 2-column halo on each side for the RW rows.  Blocks of 4 waves
 // take 4 consecutive tiles along x; blocks are remapped so that each XCD owns a
 // contiguous band of tiles.
+//
+// Alternative Laplacians for comparison (StageArgs::stencil): the non-compact
+// fourth-order stencil (-Psi_{+-2} + 16 Psi_{+-1} - 30 Psi) / (12 h^2) per axis,
+// the one 2SHOC is measured against in Sec. 2.1 and Sec. 5, with odd-reflection
+// ghosts 2 Psi_b - Psi_{b+-1} one node beyond the boundary; and the second-order
+// central difference (CD) D^x + D^y.  Both read only what the 2SHOC tile already
+// holds (two halo rows in registers, two halo columns in LDS).
 #include "tile2d.h"
 
 namespace nlse {
 
-template <typename IN, typename R, typename M, int RW>
+template <typename IN, typename R, typename M, int RW, int ST>
 __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs A, int64_t tiles_x, int64_t tiles_total)
 {
     constexpr int NW = 4;
     __shared__ C<R> lds[NW][RW][TILE_W + 4];      // Psi rows, columns x0-2 .. x0+65
     __shared__ C<R> ldx[NW][RW][TILE_W + 2];      // D^x rows, columns x0-1 .. x0+64
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6);
-    stage2d_tile<IN, R, M, RW, NW>(A, tile, tiles_x, tiles_total, lds, ldx);
+    stage2d_tile<IN, R, M, RW, NW, ST>(A, tile, tiles_x, tiles_total, lds, ldx);
 }
 
-template <typename IN, typename R, typename M, int RW>
+template <typename IN, typename R, typename M, int RW, int ST>
 static hipError_t launch_rw(const StageArgs &a, hipStream_t st)
 {
     const int64_t tiles_x = (a.L.nx - 1 + 63) / 64;
     const int64_t tiles_y = (a.L.ny - 1 + RW - 1) / RW;
     const int64_t tiles = tiles_x * tiles_y;
     const int64_t blocks = (tiles + 3) / 4;
-    hipLaunchKernelGGL((stage2d_kernel<IN, R, M, RW>), dim3((unsigned)blocks), dim3(256), 0, st, a,
+    hipLaunchKernelGGL((stage2d_kernel<IN, R, M, RW, ST>), dim3((unsigned)blocks), dim3(256), 0, st, a,
                        tiles_x, tiles);
     return hipGetLastError();
+}
+
+template <typename IN, typename R, typename M, int ST>
+static hipError_t launch2s(const StageArgs &a, hipStream_t st)
+{
+    switch (a.variant) {
+    case 0: return launch_rw<IN, R, M, 8, ST>(a, st);
+    case 1: return launch_rw<IN, R, M, 4, ST>(a, st);
+    case 2: return launch_rw<IN, R, M, 16, ST>(a, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename IN, typename R, typename M>
 static hipError_t launch2v(const StageArgs &a, hipStream_t st)
 {
-    switch (a.variant) {
-    case 0: return launch_rw<IN, R, M, 8>(a, st);
-    case 1: return launch_rw<IN, R, M, 4>(a, st);
-    case 2: return launch_rw<IN, R, M, 16>(a, st);
+    switch (a.stencil) {
+    case 0: return launch2s<IN, R, M, 0>(a, st);
+    case 1: return launch2s<IN, R, M, 1>(a, st);
+    case 2: return launch2s<IN, R, M, 2>(a, st);
     default: return hipErrorInvalidValue;
     }
 }

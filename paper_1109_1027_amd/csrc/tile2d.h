@@ -15,7 +15,9 @@ template <typename T> struct same_t<T, T> { static constexpr bool v = true; };
 
 constexpr int TILE_W = 64;
 
-template <typename IN, typename R, typename M, int RW, int NW>
+// ST selects the Laplacian: 0 the per-axis 2SHOC form, 1 the non-compact fourth-order
+// stencil (odd-reflection ghosts one node beyond the boundary), 2 the second-order CD.
+template <typename IN, typename R, typename M, int RW, int NW, int ST = 0>
 __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, int64_t tiles_x, int64_t tiles_total,
                                              C<R> (*lds)[RW][TILE_W + 4], C<R> (*ldx)[RW][TILE_W + 2])
 {
@@ -117,7 +119,22 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
     for (int r = 0; r < RW; ++r) {
         const int64_t y = y0 + r;
         if (!(xnode && x < L.nx && y < L.ny)) continue;
-        const C<R> lap = lap2<R>(dx[r], dy[r + 1], ldx[wv][r][lane], ldx[wv][r][lane + 2], dy[r], dy[r + 2], c76, c112);
+        C<R> lap;
+        if constexpr (ST == 0) {
+            lap = lap2<R>(dx[r], dy[r + 1], ldx[wv][r][lane], ldx[wv][r][lane + 2], dy[r], dy[r + 2], c76, c112);
+        } else if constexpr (ST == 2) {
+            lap = cadd<R>(dx[r], dy[r + 1]);
+        } else {
+            const R i12h2 = (R)(A.c.ih2 / 12.0);
+            const C<R> c = col[r + 2];
+            const C<R> xm1 = lds[wv][r][lane + 1], xp1 = lds[wv][r][lane + 3];
+            const C<R> xm2 = x == 1 ? ghost<R>(xm1, c) : lds[wv][r][lane];
+            const C<R> xp2 = x == L.nx - 1 ? ghost<R>(xp1, c) : lds[wv][r][lane + 4];
+            const C<R> ym1 = col[r + 1], yp1 = col[r + 3];
+            const C<R> ym2 = y == 1 ? ghost<R>(ym1, c) : col[r];
+            const C<R> yp2 = y == L.ny - 1 ? ghost<R>(yp1, c) : col[r + 4];
+            lap = cadd<R>(d4nc<R>(xm2, xm1, c, xp1, xp2, i12h2), d4nc<R>(ym2, ym1, c, yp1, yp2, i12h2));
+        }
         const C<R> u = col[r + 2];
         const C<R> F = rhs<R>(lap, u, vv[r], a, s);
         const int64_t p = L.idx(x, y, 0);

@@ -37,6 +37,7 @@ class Params(ctypes.Structure):
 EXPORTS = ["nlse_create", "nlse_set_field", "nlse_step", "nlse_get_field", "nlse_mass", "nlse_energy",
            "nlse_max_dt", "nlse_sync", "nlse_destroy", "nlse_last_error", "nlse_launches_per_step",
            "nlse_variant_count", "nlse_set_variant", "nlse_get_variant", "nlse_autotune",
+           "nlse_set_stencil", "nlse_get_stencil",
            "nlse_batch_create", "nlse_batch_count", "nlse_batch_set_field", "nlse_batch_get_field",
            "nlse_batch_set_dt", "nlse_batch_max_dt", "nlse_batch_mass", "nlse_batch_step", "nlse_batch_sync",
            "nlse_batch_variant_count", "nlse_batch_set_variant", "nlse_batch_get_variant",
@@ -72,6 +73,8 @@ def load():
     L.nlse_variant_count.argtypes = [vp]
     L.nlse_set_variant.argtypes = [vp, ctypes.c_int]
     L.nlse_get_variant.argtypes = [vp]
+    L.nlse_set_stencil.argtypes = [vp, ctypes.c_int32]
+    L.nlse_get_stencil.argtypes = [vp]
     L.nlse_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     i32 = ctypes.c_int32
     L.nlse_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), i32]
@@ -243,6 +246,19 @@ class Solver:
     @variant.setter
     def variant(self, v):
         _check(load().nlse_set_variant(self._h, int(v)))
+
+    # ---- Laplacian (2D): "2shoc" (default), "noncompact", "cd"
+    STENCILS = {"2shoc": 0, "noncompact": 1, "cd": 2}
+
+    @property
+    def stencil(self):
+        v = load().nlse_get_stencil(self._h)
+        names = {c: k for k, c in self.STENCILS.items()}
+        return names.get(v, v)
+
+    @stencil.setter
+    def stencil(self, name):
+        _check(load().nlse_set_stencil(self._h, self.STENCILS[name]))
 
     def autotune(self, reps=5, force=False):
         """Time RK4 steps of every kernel variant on this problem, keep the fastest; returns its index."""

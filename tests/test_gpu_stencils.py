@@ -1,0 +1,96 @@
+"""The alternative 2D Laplacians of the stage kernel (nlse_set_stencil) against the oracle.
+
+The non-compact fourth-order stencil and the second-order CD are what 2SHOC is compared with
+(Sec. 2.1, Sec. 5).  The oracle implements both (lap="noncompact" with odd-reflection ghosts
+beyond the boundary, lap="cd"); parity bars as for 2SHOC: FP64 <= 1e-12, FP32 <= 1e-4 relative
+L2.  Non-zero Dirichlet values make the ghosts matter.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import nlse_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-4, "mixed": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1109_1027_amd as P
+    P.load()
+    return P
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a, np.complex128) - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def with_random_boundary(spec, seed=5, amp=0.3):
+    rng = np.random.default_rng(seed)
+    psi = spec.psi0.copy()
+    m = spec.grid.boundary_mask()
+    psi[m] = amp * (rng.standard_normal(m.sum()) + 1j * rng.standard_normal(m.sum()))
+    return I.ProblemSpec(spec.name + "_bnd", spec.grid, spec.a, spec.s, spec.V, psi, spec.bc)
+
+
+@pytest.mark.parametrize("stencil", ["noncompact", "cd"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+@pytest.mark.parametrize("n,boundary", [(5, False), (70, True), (150, True)])
+def test_stencil_parity_with_oracle(gpu, orc, stencil, prec, n, boundary):
+    sp = I.config_gp2d(n=n)
+    if boundary:
+        sp = with_random_boundary(sp)
+    P = orc.Problem.from_spec(sp, lap=stencil)
+    dt = 0.5 * orc.Problem.from_spec(sp).max_dt(sp.psi0)
+    ref = P.rk4(sp.psi0, 20, dt)
+    s = gpu.Solver.from_spec(sp, prec=prec)
+    s.stencil = stencil
+    assert s.stencil == stencil
+    s.set_field(sp.psi0)
+    s.step(20, dt)
+    e = rel(s.get_field(), ref)
+    say(f"[result] {stencil} {prec} n={n}: rel L2 {e:.3e}")
+    assert e <= TOL[prec]
+
+
+@pytest.mark.parametrize("stencil", ["noncompact", "cd"])
+def test_stencil_variants_bitwise_and_api(gpu, stencil):
+    sp = with_random_boundary(I.config_gp2d(n=150))
+    s0 = gpu.Solver.from_spec(sp, prec="f32")
+    n_all = s0.variant_count()
+    s0.variant = n_all - 1                 # a whole-step variant
+    s0.stencil = stencil
+    assert s0.variant == 0 and s0.variant_count() == 3
+    outs = []
+    for v in range(3):
+        s = gpu.Solver.from_spec(sp, prec="f32")
+        s.stencil = stencil
+        s.set_field(sp.psi0)
+        s.variant = v
+        assert s.launches_per_step() == 4
+        s.step(6, 0.5 * s.max_dt())
+        outs.append(s.get_field())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    with pytest.raises(gpu.NLSEError):
+        s0.variant = 3
+    s0.stencil = "2shoc"
+    assert s0.variant_count() == n_all
+
+
+def test_stencil_unsupported_outside_2d(gpu):
+    sp1 = I.config_soliton_1d(256)
+    s = gpu.Solver.from_spec(sp1)
+    with pytest.raises(gpu.NLSEError):
+        s.stencil = "cd"
+    assert s.stencil == "2shoc"
