@@ -146,22 +146,34 @@ def copy_ceiling_gbs():
     return 10 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
-def cpu_baseline(spec, budget_s=12.0):
-    """The FP64 oracle on the same grid, a bounded number of RK4 steps on the host cores."""
+def cpu_baseline(spec, budget_s=12.0, budget_1core_s=6.0):
+    """The FP64 oracle on the same grid, a bounded number of RK4 steps on the host cores
+    (all of them, then one)."""
     import oracle
     P = oracle.Problem.from_spec(spec)
     dt = 0.5 * P.max_dt(spec.psi0)
-    psi = spec.psi0
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        psi = P.rk4(psi, 1, dt)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 50:
-            break
+
+    def run(budget, cap):
+        psi, steps, t0 = spec.psi0, 0, time.perf_counter()
+        while True:
+            psi = P.rk4(psi, 1, dt)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget or steps >= cap:
+                return steps, el
+
+    cores = oracle.threads()
+    steps, el = run(budget_s, 50)
+    oracle.set_threads(1)
+    try:
+        steps1, el1 = run(budget_1core_s, 10)
+    finally:
+        oracle.set_threads(cores)
     return {"value": spec.interior_points * steps / el / 1e9, "unit": "Gpt·steps/s",
-            "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{steps} RK4 steps of the FP64 oracle on the full 2049^2 grid ({el:.1f} s)"}
+            "cores": cores, "kind": "oracle",
+            "sample": f"{steps} RK4 steps of the FP64 oracle on the full {spec.grid.n + 1}^2 grid ({el:.1f} s, {cores} threads); "
+                      f"{steps1} steps on 1 thread ({el1:.1f} s)",
+            "single_core_value": spec.interior_points * steps1 / el1 / 1e9}
 
 
 def bench_3d(P, I, args):

@@ -13,7 +13,7 @@
 // arrives, stage 1 produces row j-2 of its output, stage 2 row j-4, stage 3
 // row j-6 and stage 4 row j-8 of Psi^{n+1}.  Along y each stage keeps its last
 // three input rows and three D^y rows in registers; along x the neighbours come
-// from the adjacent lanes through DPP wave shifts (no LDS, no barriers).  The
+// from the adjacent lanes through DPP wave shifts (no LDS exchange, no barriers).  The
 // valid columns shrink by two per side and stage, so the middle 48 of the 64
 // lanes produce Psi^{n+1}: neighbouring strips overlap by 16 columns and
 // neighbouring segments by 16 rows of recomputed halo.
