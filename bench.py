@@ -255,7 +255,7 @@ def bench_learned(P, seed=9000):
                         "with the 3-layer BF16-MFMA conv corrector every 10 steps",
             **{k: summ[k] for k in ("E_plain", "T_plain_s", "E_learned", "T_learned_s", "T_fine_s", "fit_order_p",
                                     "n_equal_error", "speedup_vs_plain_equal_error", "speedup_vs_fine",
-                                    "gain_E512_over_learned")}}
+                                    "gain_E512_over_learned", "E_fine_run_richardson")}}
 
 
 def main():

@@ -252,10 +252,15 @@ def summarize(res, sizes=(512, 1024, 1536)):
     n_star = float(np.exp((c - math.log(El)) / p)) if El > 0 else float("inf")
     lt = np.polyfit(ln, np.log([T[n] for n in sizes]), 1)
     t_star = float(np.exp(np.polyval(lt, math.log(n_star))))
+    # Richardson estimate of the reference run's own distance from the converged solution: with
+    # E(n) ~ C n^-p, |u_2048 - u_inf| ~ E(1024) 2^-p / (1 - 2^-p) (the fitted p, not the scheme's 4,
+    # because the Thomas-Fermi kink limits convergence)
+    n_half = N_FINE // 2
+    e_ref = E[n_half] * 2.0 ** (-p) / (1.0 - 2.0 ** (-p)) if n_half in E else float("nan")
     return {"E_plain": E, "T_plain_s": T, "E_learned": El, "T_learned_s": Tl, "T_fine_s": Tf,
             "fit_order_p": float(p), "n_equal_error": n_star, "T_plain_at_equal_error_s": t_star,
             "speedup_vs_plain_equal_error": t_star / Tl, "speedup_vs_fine": Tf / Tl,
-            "gain_E512_over_learned": E[sizes[0]] / El}
+            "gain_E512_over_learned": E[sizes[0]] / El, "E_fine_run_richardson": float(e_ref)}
 
 
 def main():
