@@ -25,7 +25,7 @@ GIB = float(1 << 30)
 
 # source files each kernel is compiled from (its .hip and every header it includes)
 SOURCES = {"stage2d": ["stage2d.hip", "tile2d.h", "point.h", "common.h", "kernels.h"],
-           "step2d": ["step2d.hip", "point.h", "common.h", "kernels.h"]}
+           "step2d": ["step2d.hip", "wave2d.h", "dpp.h", "point.h", "common.h", "kernels.h"]}
 KEYS = {"stage2d": {"f64": ["stage2d_kernel<double, double, double"], "f32": ["stage2d_kernel<float, float, float"],
                     "mixed": ["stage2d_kernel<double, float, double", "stage2d_kernel<float, float, double"]},
         "step2d": {"f64": ["step2d_kernel<double, double"], "f32": ["step2d_kernel<float, float"],

@@ -23,7 +23,8 @@ __all__ = [
     "Grid", "grid", "bright_soliton", "dark_soliton", "gaussian_ho",
     "gp2d_vortex", "gp3d_ring", "gp2d_multivortex", "batch_instances",
     "ProblemSpec", "config_soliton_1d", "config_gp2d", "config_gp3d",
-    "paper_fig1", "paper_fig2", "paper_fig3",
+    "paper_fig1", "paper_fig2", "paper_fig3", "dark_plane", "background_vortices",
+    "background_ring",
 ]
 
 
@@ -180,6 +181,55 @@ def gp3d_ring(g: Grid, omega=0.1, mu=1.0, ring_radius=6.0):
     return psi.astype(np.complex128), V
 
 
+def dark_plane(dim, h, t=0.0, lo=-8.0, hi=8.0, width=2.0, x0=-6.5, a=0.5, s=-1.0, mu=1.0):
+    """Stationary dark soliton plane of the defocusing NLSE (V = 0) in 1D, 2D or 3D.
+
+    Psi = sqrt(mu/|s|) tanh(sqrt(mu/(2a)) (x - x0)) e^{-i mu t}, the same on every line along x
+    (the c = 0 case of Eq. 1dmds with Omega = -mu).  x in [lo, hi], y and z in [0, width], step h.
+    Its density never changes, so the modulus-squared Dirichlet (MSD) rule holds exactly on every
+    face; with x0 near the x = lo face the density still varies steeply there.
+    Returns (intervals per axis (nx[, ny[, nz]]), psi [z][y][x])."""
+    nx, ny = int(round((hi - lo) / h)), int(round(width / h))
+    x = lo + h * np.arange(nx + 1)
+    prof = dark_soliton(x, t, a=a, s=s, omega=-mu, c=0.0, x0=x0)
+    shape = (ny + 1,) * (dim - 1) + (nx + 1,)
+    return (nx,) + (ny,) * (dim - 1), np.broadcast_to(prof, shape).astype(np.complex128)
+
+
+def background_vortices(g: Grid, mu=1.0, s=-1.0, pairs=2, noise=1e-3, seed=0):
+    """Vortex-antivortex pairs in a uniform background of density mu/|s| (V = 0), for the MSD rule.
+
+    Psi0 = sqrt(mu/|s|) prod_k tanh(|r - r_k|) e^{+-i theta_k} + noise: `pairs` pairs with their
+    centres at seeded positions within the inner 60 % of the box, one vortex of each charge 4 healing
+    lengths apart; noise as in gp2d_vortex, on every node (the boundary evolves under MSD)."""
+    rng = np.random.default_rng(seed)
+    x, y = g.coords()
+    psi = np.full(g.shape, math.sqrt(mu / abs(s)), dtype=np.complex128)
+    half = 0.3 * (g.hi - g.lo)
+    mid = 0.5 * (g.hi + g.lo)
+    for _ in range(pairs):
+        cx, cy = mid + rng.uniform(-half, half), mid + rng.uniform(-half, half)
+        ang = rng.uniform(0, 2 * math.pi)
+        for sgn in (1.0, -1.0):
+            xk, yk = cx + sgn * 2.0 * math.cos(ang), cy + sgn * 2.0 * math.sin(ang)
+            dx, dy = x - xk, y - yk
+            psi = psi * np.tanh(np.sqrt(dx * dx + dy * dy)) * np.exp(1j * sgn * np.arctan2(dy, dx))
+    if noise:
+        psi = psi + _noise(rng, g.shape, noise, np.ones(g.shape))
+    return psi.astype(np.complex128)
+
+
+def background_ring(g: Grid, mu=1.0, s=-1.0, ring_radius=4.0):
+    """Vortex ring of given radius in the z = 0 plane in a uniform background (V = 0), 3D.
+
+    Psi0 = sqrt(mu/|s|) tanh(d) e^{i atan2(z, rho - R)}, d the distance to the ring's core line."""
+    x, y, z = g.coords()
+    rho = np.sqrt(x * x + y * y)
+    d = np.sqrt((rho - ring_radius) ** 2 + z * z)
+    psi = math.sqrt(mu / abs(s)) * np.tanh(d) * np.exp(1j * np.arctan2(z, rho - ring_radius))
+    return psi.astype(np.complex128)
+
+
 # ---------------------------------------------------------------------------
 # Workload definitions
 # ---------------------------------------------------------------------------
@@ -193,7 +243,7 @@ class ProblemSpec:
     s: float
     V: np.ndarray | None
     psi0: np.ndarray
-    bc: str = "dirichlet"          # or "msd" (1D only)
+    bc: str = "dirichlet"          # or "msd"
     t_end: float | None = None
     steps: int | None = None
 

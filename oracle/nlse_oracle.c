@@ -12,7 +12,9 @@
  * Every step follows the paper in its own order and notation:
  *   - step 1 of 2SHOC, the second-order difference D (Sec. 2.1 Eq. 2shoc1d;
  *     Sec. 2.2 Eq. 2d2shocs1; Sec. 2.3 Eq. 3d2shocs);
- *   - the boundary closure of step 1 (Sec. 3.2: Dirichlet Eq. dbc_lap, MSD Eq. msdbc_lap);
+ *   - the boundary closure of step 1 (Sec. 3.2: Dirichlet Eq. dbc_lap, MSD Eq. msdbc_lap,
+ *     in 1D and, with the paper's remark that MSD carries over to several
+ *     dimensions, in 2D/3D with b-1 the closest interior node);
  *   - step 2 of 2SHOC in the single-storage form (Eq. 2shoc1d2, 2d2shocs2, 3d2shocs2);
  *   - F(Psi) = i[a Lap + (s|Psi|^2 - V) Psi] on the interior, then the boundary
  *     time derivative (Eq. dbc_ut, Eq. msdbc_ut), interior first, boundary second;
@@ -48,7 +50,7 @@ typedef struct {
     long n[3];        /* intervals per axis (unused axes ignored) */
     double h, a, s;   /* grid step (same on every axis), a > 0, s */
     const double *V;  /* real potential on every node, or NULL for V = 0 */
-    int bc;           /* ORC_DIRICHLET or ORC_MSD (MSD: 1D only) */
+    int bc;           /* ORC_DIRICHLET or ORC_MSD */
     int lap;          /* ORC_LAP_* */
 } orc_problem;
 
@@ -104,7 +106,6 @@ static int validate(const orc_problem *P)
         if (P->n[a] < 2) return -1;
     if (!(P->h > 0.0) || !(P->a > 0.0)) return -1;
     if (P->bc != ORC_DIRICHLET && P->bc != ORC_MSD) return -1;
-    if (P->bc == ORC_MSD && P->dim != 1) return -2;   /* multi-D MSD: not given by the paper */
     if (P->lap < ORC_LAP_2SHOC || P->lap > ORC_LAP_CD) return -1;
     return 0;
 }
@@ -141,9 +142,26 @@ static zd dirichlet_lap_b(const orc_problem *P, const zd *psi, long b)
     return -(nonlin(P, psi, b) * psi[b]) / P->a;
 }
 
-/* MSD closure of step 1 in 1D (Eq. msdbc_lap):
+/* The node b-1 of the MSD rule for boundary node p (Sec. 3.2): the closest
+ * interior node, one step inward along every axis on which p is a boundary
+ * node.  For a face node that is the inward neighbour in the normal direction,
+ * as the paper defines it; for an edge or corner node (boundary in two or three
+ * axes, where the normal is not defined) it is the diagonal interior neighbour. */
+static long msd_inner(const orc_problem *P, const geom *g, long p)
+{
+    long idx[3];
+    coords_of(g, p, idx);
+    long q = p;
+    for (int a = 0; a < P->dim; ++a) {
+        if (idx[a] == 0) q += g->st[a];
+        else if (idx[a] == P->n[a]) q -= g->st[a];
+    }
+    return q;
+}
+
+/* MSD closure of step 1 (Eq. msdbc_lap):
  *   Lap Psi_b = [ Im(i D_{b-1} / Psi_{b-1}) + (N_{b-1} - N_b) / a ] Psi_b,
- * with Im(i z) = Re(z).  D_{b-1} is the step-1 value at the inner neighbour.
+ * with Im(i z) = Re(z).  D_{b-1} is the step-1 value at the inner node b-1.
  * A zero inner value leaves the ratio term out. */
 static zd msd_lap_b(const orc_problem *P, const zd *psi, const zd *D, long b, long bm1)
 {
@@ -155,16 +173,12 @@ static zd msd_lap_b(const orc_problem *P, const zd *psi, const zd *D, long b, lo
 
 static void step1_boundary(const orc_problem *P, const geom *g, const zd *psi, zd *D)
 {
-    if (P->bc == ORC_MSD) {   /* 1D: interior first (already done), boundary second */
-        long n = P->n[0];
-        D[0] = msd_lap_b(P, psi, D, 0, 1);
-        D[n] = msd_lap_b(P, psi, D, n, n - 1);
-        return;
-    }
+    /* interior first (already done), boundary second; b-1 is always interior */
     for (long p = 0; p < g->total; ++p) {
         long idx[3];
         coords_of(g, p, idx);
-        if (!is_interior(P, idx)) D[p] = dirichlet_lap_b(P, psi, p);
+        if (is_interior(P, idx)) continue;
+        D[p] = P->bc == ORC_MSD ? msd_lap_b(P, psi, D, p, msd_inner(P, g, p)) : dirichlet_lap_b(P, psi, p);
     }
 }
 
@@ -214,7 +228,7 @@ static void lap_per_axis(const orc_problem *P, const geom *g, const zd *psi, zd 
     zd *Da[3] = {NULL, NULL, NULL};
     for (int a = 0; a < P->dim; ++a) Da[a] = calloc((size_t)g->total, sizeof(zd));
     zd *Dfull = calloc((size_t)g->total, sizeof(zd));
-    /* full step-1 array, needed only for the MSD (1D) boundary value */
+    /* full step-1 array: its boundary entries are the step-1 closure Lap_b */
     step1_interior(P, g, psi, Dfull);
     step1_boundary(P, g, psi, Dfull);
     for (long p = 0; p < g->total; ++p) {
@@ -321,11 +335,12 @@ static void rhs(const orc_problem *P, const geom *g, const zd *psi, zd *F, zd *l
                 if (!is_interior(P, idx)) { F[p] = 0.0; continue; }
                 F[p] = times_i(P->a * lap[p] + nonlin(P, psi, p) * psi[p]);
             }
-    if (P->bc == ORC_MSD) {
-        long n = P->n[0];
-        long bs[2] = {0, n}, ins[2] = {1, n - 1};
-        for (int t = 0; t < 2; ++t) {
-            long b = bs[t], bm1 = ins[t];
+    if (P->bc == ORC_MSD) {   /* every interior F first, then the boundary */
+        for (long b = 0; b < g->total; ++b) {
+            long idx[3];
+            coords_of(g, b, idx);
+            if (is_interior(P, idx)) continue;
+            long bm1 = msd_inner(P, g, b);
             double im = 0.0;
             if (psi[bm1] != 0.0) im = cimag(F[bm1] / psi[bm1]);
             F[b] = CMPLX(0.0, im) * psi[b];
@@ -471,7 +486,8 @@ double orc_energy(const orc_problem *P, const double *psi_in)
  *   k_max = sqrt(8) h^2 / (a max(|B|_inf, max_{i,j} |L_i - G_j|)),  L_i = (h^2/a)(s|Psi_i|^2 - V_i)
  * over interior nodes.  Only the extreme G values matter:
  *   max_{i,j} |L_i - G_j| = max(G_max - L_min, L_max - G_min).
- * B_b = 0 for Dirichlet; for MSD B_b = (h^2/(i a)) F_{b-1}/Psi_{b-1}.
+ * B_b = 0 for Dirichlet; for MSD B_b = (h^2/(i a)) F_{b-1}/Psi_{b-1}, over every node b-1
+ * that the MSD rule reads (the interior nodes next to the boundary).
  * Also returns L_min, L_max and |B|_inf through the optional out array (3 doubles). */
 double orc_max_dt(const orc_problem *P, const double *psi_in, double *aux)
 {
@@ -494,9 +510,11 @@ double orc_max_dt(const orc_problem *P, const double *psi_in, double *aux)
         zd *F = calloc((size_t)g.total, sizeof(zd)), *D = calloc((size_t)g.total, sizeof(zd));
         zd *lap = calloc((size_t)g.total, sizeof(zd));
         rhs(P, &g, psi, F, lap, D);
-        long ins[2] = {1, P->n[0] - 1};
-        for (int t = 0; t < 2; ++t) {
-            long q = ins[t];
+        for (long b = 0; b < g.total; ++b) {
+            long idx[3];
+            coords_of(&g, b, idx);
+            if (is_interior(P, idx)) continue;
+            long q = msd_inner(P, &g, b);
             if (psi[q] != 0.0) {
                 double B = h2a * cabs(F[q] / psi[q]);
                 if (B > bmax) bmax = B;
