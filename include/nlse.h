@@ -9,8 +9,8 @@
  * four times; Lap is the two-step high-order compact (2SHOC) Laplacian
  * (Sec. 2.1-2.3): step 1 a second difference D, step 2 a compact combination of
  * D that is fourth-order accurate.  Boundary closures follow Sec. 3.2 (Dirichlet
- * Eqs. dbc_lap / dbc_ut; modulus-squared Dirichlet, 1D only, Eqs. msdbc_lap /
- * msdbc_ut).  Every step runs in hand-written HIP kernels on the GPU.
+ * Eqs. dbc_lap / dbc_ut; modulus-squared Dirichlet, Eqs. msdbc_lap / msdbc_ut, in
+ * 1D, 2D and 3D).  Every step runs in hand-written HIP kernels on the GPU.
  *
  * Conventions shared by every entry point
  *   - Grid: n[a] intervals per axis, n[a] + 1 nodes including both boundary
@@ -49,7 +49,8 @@ typedef enum {
     NLSE_E_NONFINITE = -3,     /* a reduction met NaN or Inf in the field */
     NLSE_E_NOMEM = -4,         /* device allocation failed */
     NLSE_E_HIP = -5,           /* a HIP runtime call failed */
-    NLSE_E_UNSUPPORTED = -6    /* valid but not implemented (e.g. MSD in 2D/3D) */
+    NLSE_E_UNSUPPORTED = -6    /* valid but not implemented (e.g. a 1D field too large
+                                  for the on-chip solver) */
 } nlse_status;
 
 typedef enum {
@@ -64,7 +65,12 @@ typedef enum {
 typedef enum {
     NLSE_BC_DIRICHLET = 0, /* boundary nodes keep their initial values (Eq. dbc_ut);
                               step-1 boundary value from Eq. dbc_lap */
-    NLSE_BC_MSD = 1        /* |Psi_b|^2 constant (Eqs. msdbc_ut, msdbc_lap); 1D only */
+    NLSE_BC_MSD = 1        /* |Psi_b|^2 constant (Eqs. msdbc_ut, msdbc_lap).  b-1 is the
+                              closest interior node: the normal neighbour on a face, the
+                              diagonal one on an edge or corner (2D/3D; Sec. 3.2 says the rule
+                              carries over to several dimensions, the corner choice is ours).
+                              1D needs n >= 4 intervals.  2D/3D run the stage kernels with two
+                              small boundary launches per stage */
 } nlse_bc;
 
 typedef enum {
@@ -92,7 +98,7 @@ typedef struct {
 /* Create a context: validates params, allocates the resident device arrays
  * (Psi^n, two ping-pong stage fields, K_tot, V) and copies V.  The field is
  * zero until nlse_set_field.  Returns NLSE_E_INVAL for invalid params and
- * NLSE_E_UNSUPPORTED for MSD with ndim > 1. */
+ * NLSE_E_UNSUPPORTED for a 1D field larger than the on-chip solver holds. */
 int nlse_create(nlse_ctx **out, const nlse_params *p);
 
 /* Copy a full field (all (n+1)^ndim nodes, boundary included) into the context.
@@ -123,7 +129,7 @@ int nlse_energy(nlse_ctx *c, double *out);
  *   L_i = (h^2/a)(s|Psi_i|^2 - V_i) over interior nodes, (G_max, G_min) =
  *   (64, -4)/12, (128, -8)/12, (192, -12)/12 in 1D / 2D / 3D (Table
  *   t:sumresults), B_b = 0 for Dirichlet and (h^2/(i a)) F_{b-1}/Psi_{b-1} for
- *   MSD (Table t:bc2). */
+ *   MSD (Table t:bc2), over every node b-1 the MSD rule reads. */
 int nlse_max_dt(nlse_ctx *c, double *out);
 
 /* Wait until all work enqueued by the context has finished. */
@@ -136,14 +142,16 @@ void nlse_destroy(nlse_ctx *c);
 const char *nlse_last_error(void);
 
 /* Number of kernel launches one RK4 step enqueues for this context with its current
- * variant: 4 for the 2D/3D stage kernels, 1 for the 2D whole-step kernels; 1D contexts
+ * variant: 4 for the 2D/3D stage kernels (12 under MSD: face values and boundary update
+ * around each stage), 1 for the 2D whole-step kernels (Dirichlet only); 1D contexts
  * advance all steps in one launch and report 0.  For throughput accounting. */
 int nlse_launches_per_step(const nlse_ctx *c);
 
 /* Kernel variants.  2D: 0-2 are the stage kernels (one launch per RK4 stage, tiles of
  * 64 columns x 8, 4 or 16 rows per wave); 3-8 the whole-step kernels (one launch per RK4
  * step, Sec. 3.1 with all four stages fused; a wave walks a 64-column strip down a segment
- * of 29, 20, 38, 56, 11 or 47 rows; offered when the padded field has fewer than 2^31 elements).
+ * of 29, 20, 38, 56, 11 or 47 rows; offered under Dirichlet when the padded field has fewer
+ * than 2^31 elements).
  * 3D: stage kernels with 64 x 4 or 64 x 8 column tiles marching 16, 32 or 64 planes.
  * Every variant computes bit-identical fields; they differ only in speed.  1D contexts
  * have one. */
@@ -173,7 +181,8 @@ int nlse_autotune(nlse_ctx *c, int reps, int force, int *chosen);
 /* ---------------------------------------------------------------- batches --
  * Many independent 1D / 2D problems of uneven size advanced together by one
  * persistent kernel launch (captured in a hipGraph).  Each instance has its own
- * grid, coefficients, potential, boundary rule (MSD for 1D) and step dt; all
+ * grid, coefficients, potential, boundary rule (MSD for 1D only: 2D instances
+ * with MSD give NLSE_E_UNSUPPORTED) and step dt; all
  * share the precision and the stream of items[0].  Workgroups take instances
  * longest-first from a device queue; a 1D instance (at most 8704 nodes in FP32 /
  * mixed, 5120 in FP64) runs entirely on chip, a 2D instance is swept tile by tile

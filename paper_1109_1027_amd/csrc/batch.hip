@@ -267,6 +267,8 @@ int nlse_batch_create(nlse_batch **out, const nlse_params *items, int32_t count)
     for (int i = 0; i < count; ++i) {
         if (items[i].ndim != 1 && items[i].ndim != 2)
             return fail(NLSE_E_UNSUPPORTED, "batched instances are 1D or 2D");
+        if (items[i].ndim == 2 && items[i].bc != NLSE_BC_DIRICHLET)
+            return fail(NLSE_E_UNSUPPORTED, "batched 2D instances take the Dirichlet boundary");
         if (items[i].prec != items[0].prec) return fail(NLSE_E_INVAL, "all instances need the same precision");
         if (items[i].stream != items[0].stream) return fail(NLSE_E_INVAL, "all instances need the same stream");
     }

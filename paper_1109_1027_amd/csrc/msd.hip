@@ -1,0 +1,334 @@
+// The modulus-squared Dirichlet (MSD) boundary in 2D and 3D (Sec. 3.2).
+//
+// The paper gives the MSD rule for a boundary node b in terms of b-1, the nearest
+// interior node in the normal direction, and notes that it carries over to
+// several dimensions.  Here b-1 is the closest interior node: one step inward
+// along every axis on which b is a boundary node (the normal neighbour on a face,
+// the diagonal interior neighbour on an edge or corner, where no normal exists).
+//
+//   step 1 (Eq. msdbc_lap):  Lap_b = [Re(D_{b-1} / Psi_{b-1}) + (N_{b-1} - N_b) / a] Psi_b
+//   time derivative (Eq. msdbc_ut):  F_b = i Im(F_{b-1} / Psi_{b-1}) Psi_b
+//   N = s |Psi|^2 - V (Eq. nbnb1); a zero Psi_{b-1} drops the ratio term.
+//
+// The interior stage kernels (per-axis 2SHOC) read, on a face node normal to axis
+// a, the value D^a_b = Lap_b - (second differences along the face), the closure
+// under which the per-axis form equals the single-storage one.  Under Dirichlet
+// those values are constants; under MSD they follow the field, so every RK4 stage
+// runs three launches:
+//   1. msd_face_kernel    D^a_b on every face node from the stage's input field;
+//   2. the interior stage kernel (unchanged: it reads the face values);
+//   3. msd_update_kernel  F_b from F_{b-1}, recomputed from the same input and face
+//      values (interior first, boundary second), and the stage's RK4 array
+//      operations on the boundary nodes.
+// The boundary work is O(n^(d-1)) against the interior's O(n^d).
+#include "kernels.h"
+#include "point.h"
+
+namespace nlse {
+
+namespace {
+
+template <typename T, typename U> struct same_m { static constexpr bool v = false; };
+template <typename T> struct same_m<T, T> { static constexpr bool v = true; };
+
+struct Node {
+    int64_t c[3];
+};
+
+__device__ __forceinline__ int64_t ext(const Layout &L, int a) { return a == 0 ? L.nx : a == 1 ? L.ny : L.nz; }
+
+__device__ __forceinline__ bool on_bnd(const Layout &L, const Node &q, int a)
+{
+    return a < L.dim && (q.c[a] == 0 || q.c[a] == ext(L, a));
+}
+
+__device__ __forceinline__ Node step(Node q, int a, int d)
+{
+    q.c[a] += d;
+    return q;
+}
+
+// Index of node q within the face normal to axis a (layout of the face arrays):
+// a = x: z (ny+1) + y;  a = y: z (nx+1) + x;  a = z: y (nx+1) + x.
+__device__ __forceinline__ int64_t face_index(const Layout &L, int a, const Node &q)
+{
+    const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+    int64_t fi = q.c[t1];
+    if (t2 < L.dim) fi += q.c[t2] * (ext(L, t1) + 1);
+    return fi;
+}
+
+__device__ __forceinline__ int64_t face_size(const Layout &L, int a)
+{
+    int64_t f = 1;
+    for (int b = 0; b < L.dim; ++b)
+        if (b != a) f *= ext(L, b) + 1;
+    return f;
+}
+
+// The boundary node of face (axis a, side) with face index fi.
+__device__ __forceinline__ Node face_node(const Layout &L, int a, int side, int64_t fi)
+{
+    const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+    Node q;
+    q.c[0] = q.c[1] = q.c[2] = 0;
+    q.c[a] = side ? ext(L, a) : 0;
+    const int64_t m1 = ext(L, t1) + 1;
+    q.c[t1] = fi % m1;
+    if (t2 < L.dim) q.c[t2] = fi / m1;
+    return q;
+}
+
+// b-1 of the MSD rule: one step inward along every boundary axis of b.
+__device__ __forceinline__ Node inner(const Layout &L, Node b)
+{
+    for (int a = 0; a < L.dim; ++a) {
+        if (b.c[a] == 0) b.c[a] = 1;
+        else if (b.c[a] == ext(L, a)) b.c[a] = ext(L, a) - 1;
+    }
+    return b;
+}
+
+template <typename IN, typename R>
+struct Field {
+    const C<IN> *in;
+    const R *V;
+    Layout L;
+    __device__ __forceinline__ C<R> psi(const Node &q) const { return cvt<R, IN>(in[L.idx(q.c[0], q.c[1], q.c[2])]); }
+    __device__ __forceinline__ R pot(const Node &q) const { return V ? V[L.idx(q.c[0], q.c[1], q.c[2])] : R(0); }
+    // delta_a^2 Psi at q (q +- e_a inside the grid)
+    __device__ __forceinline__ C<R> d2a(const Node &q, int a, R ih2) const
+    {
+        return d2<R>(psi(step(q, a, -1)), psi(q), psi(step(q, a, 1)), ih2);
+    }
+};
+
+// The face value D^a read by the interior kernels at node r (r on the face normal to a).
+template <typename R>
+__device__ __forceinline__ C<R> face_value(const Layout &L, const C<R> *const DB[3], int a, const Node &r)
+{
+    const int side = r.c[a] == 0 ? 0 : 1;
+    return DB[a][side * face_size(L, a) + face_index(L, a, r)];
+}
+
+// F at the interior node q, per-axis 2SHOC (Eqs. 2d2shocMs1-2, 3d2shocMs1-2) with the face
+// values where q's neighbour along an axis is a boundary node.
+template <typename IN, typename R>
+__device__ C<R> interior_F(const Field<IN, R> &f, const C<R> *const DB[3], const Coeffs &cf, const Node &q)
+{
+    const R ih2 = (R)cf.ih2, c76 = (R)cf.c76, c112 = (R)cf.c112;
+    C<R> dc[3], dl[3], dr[3];
+    for (int a = 0; a < f.L.dim; ++a) {
+        dc[a] = f.d2a(q, a, ih2);
+        const Node lo = step(q, a, -1), hi = step(q, a, 1);
+        dl[a] = lo.c[a] == 0 ? face_value<R>(f.L, DB, a, lo) : f.d2a(lo, a, ih2);
+        dr[a] = hi.c[a] == ext(f.L, a) ? face_value<R>(f.L, DB, a, hi) : f.d2a(hi, a, ih2);
+    }
+    C<R> lap;
+    if (f.L.dim == 2) {
+        lap = lap2<R>(dc[0], dc[1], dl[0], dr[0], dl[1], dr[1], c76, c112);
+    } else {
+#pragma clang fp contract(off)
+        const R ax = (dc[0].x + dc[1].x) + dc[2].x, ay = (dc[0].y + dc[1].y) + dc[2].y;
+        const R bx = ((dr[0].x + dl[0].x) + (dr[1].x + dl[1].x)) + (dr[2].x + dl[2].x);
+        const R by = ((dr[0].y + dl[0].y) + (dr[1].y + dl[1].y)) + (dr[2].y + dl[2].y);
+        lap = mk<R>(fmar(c76, ax, -(c112 * bx)), fmar(c76, ay, -(c112 * by)));
+    }
+    return rhs<R>(lap, f.psi(q), f.pot(q), (R)cf.a, (R)cf.s);
+}
+
+// Im(F_q / Psi_q), 0 when Psi_q = 0.
+template <typename R>
+__device__ __forceinline__ R phase_rate(const C<R> &F, const C<R> &u)
+{
+    const R den = u.x * u.x + u.y * u.y;
+    return den != R(0) ? (F.y * u.x - F.x * u.y) / den : R(0);
+}
+
+// ---- 1. face values D^a_b from the stage input -------------------------------------------
+
+template <typename IN, typename R>
+__global__ void msd_face_kernel(Field<IN, R> f, Coeffs cf, C<R> *DBx, C<R> *DBy, C<R> *DBz)
+{
+    const int a = blockIdx.y, side = blockIdx.z;
+    const Layout &L = f.L;
+    if (a >= L.dim) return;
+    const int64_t fi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (fi >= face_size(L, a)) return;
+    const Node b = face_node(L, a, side, fi);
+    for (int t = 0; t < L.dim; ++t)
+        if (t != a && on_bnd(L, b, t)) return;   // edge / corner: never read by the stage kernels
+    const R ih2 = (R)cf.ih2, s = (R)cf.s;
+    const Node q = step(b, a, side ? -1 : 1);
+    const C<R> ub = f.psi(b), uq = f.psi(q);
+    C<R> Dq = czero<R>();   // the full step-1 value at b-1 (Eqs. 2d2shocs1, 3d2shocs)
+    for (int t = 0; t < L.dim; ++t) Dq = cadd<R>(Dq, f.d2a(q, t, ih2));
+    const R den = uq.x * uq.x + uq.y * uq.y;
+    const R ratio = den != R(0) ? (Dq.x * uq.x + Dq.y * uq.y) / den : R(0);
+    const R fac = ratio + (nonlin<R>(uq, f.pot(q), s) - nonlin<R>(ub, f.pot(b), s)) * (R)cf.ia;
+    C<R> Db = mk<R>(fac * ub.x, fac * ub.y);   // Lap_b
+    for (int t = 0; t < L.dim; ++t)
+        if (t != a) Db = csub<R>(Db, f.d2a(b, t, ih2));
+    C<R> *dst = a == 0 ? DBx : a == 1 ? DBy : DBz;
+    dst[side * face_size(L, a) + fi] = Db;
+}
+
+template <typename IN, typename R>
+static hipError_t launch_faces(const void *in, const void *V, const Layout &L, const Coeffs &c, void *const DB[3],
+                               hipStream_t st)
+{
+    int64_t maxf = 1;
+    for (int a = 0; a < L.dim; ++a) {
+        int64_t f = 1;
+        for (int b = 0; b < L.dim; ++b)
+            if (b != a) f *= (b == 0 ? L.nx : b == 1 ? L.ny : L.nz) + 1;
+        if (f > maxf) maxf = f;
+    }
+    Field<IN, R> f{(const C<IN> *)in, (const R *)V, L};
+    dim3 grid((unsigned)((maxf + 255) / 256), (unsigned)L.dim, 2);
+    hipLaunchKernelGGL((msd_face_kernel<IN, R>), grid, dim3(256), 0, st, f, c, (C<R> *)DB[0], (C<R> *)DB[1],
+                       (C<R> *)DB[2]);
+    return hipGetLastError();
+}
+
+// ---- 3. boundary F_b and the stage's RK4 operations on the boundary --------------------------
+
+// Every boundary node once: the face of the lowest axis on which it lies.
+__device__ __forceinline__ bool owner(const Layout &L, const Node &b, int a)
+{
+    for (int t = 0; t < a; ++t)
+        if (on_bnd(L, b, t)) return false;
+    return true;
+}
+
+template <typename IN, typename R, typename M>
+__global__ void msd_update_kernel(Field<IN, R> f, StageArgs A)
+{
+    const int a = blockIdx.y, side = blockIdx.z;
+    const Layout &L = f.L;
+    if (a >= L.dim) return;
+    const int64_t fi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (fi >= face_size(L, a)) return;
+    const Node b = face_node(L, a, side, fi);
+    if (!owner(L, b, a)) return;
+    const C<R> *const DB[3] = {(const C<R> *)A.DB[0], (const C<R> *)A.DB[1], (const C<R> *)A.DB[2]};
+    const Node q = inner(L, b);
+    const C<R> uq = f.psi(q), ub = f.psi(b);
+    const R w = phase_rate<R>(interior_F<IN, R>(f, DB, A.c, q), uq);
+    const C<R> F = mk<R>(-w * ub.y, w * ub.x);
+    const int64_t p = L.idx(b.c[0], b.c[1], b.c[2]);
+    const R ck = (R)A.c.ck;
+    C<M> *psin = (C<M> *)A.psin;
+    C<R> *K = (C<R> *)A.K;
+    C<R> *out = (C<R> *)A.out;
+    if (A.stage == 1) {
+        const C<M> base = same_m<IN, R>::v ? cvt<M, R>(ub) : psin[p];
+        K[p] = F;
+        out[p] = cvt<R, M>(axpy_m<R, M>(base, ck, F));
+    } else if (A.stage <= 3) {
+        K[p] = kacc<R>(K[p], F);
+        out[p] = cvt<R, M>(axpy_m<R, M>(psin[p], ck, F));
+    } else {
+        psin[p] = axpy_m<R, M>(psin[p], ck, cadd<R>(K[p], F));
+    }
+}
+
+template <typename IN, typename R, typename M>
+static hipError_t launch_update(const StageArgs &A, hipStream_t st)
+{
+    const Layout &L = A.L;
+    int64_t maxf = 1;
+    for (int a = 0; a < L.dim; ++a) {
+        int64_t f = 1;
+        for (int b = 0; b < L.dim; ++b)
+            if (b != a) f *= (b == 0 ? L.nx : b == 1 ? L.ny : L.nz) + 1;
+        if (f > maxf) maxf = f;
+    }
+    Field<IN, R> f{(const C<IN> *)A.in, (const R *)A.V, L};
+    dim3 grid((unsigned)((maxf + 255) / 256), (unsigned)L.dim, 2);
+    hipLaunchKernelGGL((msd_update_kernel<IN, R, M>), grid, dim3(256), 0, st, f, A);
+    return hipGetLastError();
+}
+
+// ---- the bound's boundary term: max over b-1 of (h^2/a) |F_{b-1} / Psi_{b-1}| -----------------
+
+template <typename IN, typename R>
+__global__ void msd_bound_kernel(Field<IN, R> f, Coeffs cf, const void *DB0, const void *DB1, const void *DB2,
+                                 double h2a, unsigned long long *out)
+{
+    const int a = blockIdx.y, side = blockIdx.z;
+    const Layout &L = f.L;
+    if (a >= L.dim) return;
+    const int64_t fi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (fi >= face_size(L, a)) return;
+    const Node b = face_node(L, a, side, fi);
+    if (!owner(L, b, a)) return;
+    const C<R> *const DB[3] = {(const C<R> *)DB0, (const C<R> *)DB1, (const C<R> *)DB2};
+    const Node q = inner(L, b);
+    const C<R> uq = f.psi(q);
+    const double den = (double)uq.x * uq.x + (double)uq.y * uq.y;
+    if (den == 0.0) return;
+    const C<R> F = interior_F<IN, R>(f, DB, cf, q);
+    const double B = h2a * sqrt(((double)F.x * F.x + (double)F.y * F.y) / den);
+    // non-negative doubles order as their bit patterns: the maximum is exact and order-free
+    atomicMax(out, (unsigned long long)__double_as_longlong(B));
+}
+
+}  // namespace
+
+hipError_t launch_msd_faces(Prec prec, bool master, const void *in, const void *V, const Layout &L,
+                            const Coeffs &c, void *const DB[3], hipStream_t st)
+{
+    switch (prec) {
+    case P_F64: return launch_faces<double, double>(in, V, L, c, DB, st);
+    case P_F32: return launch_faces<float, float>(in, V, L, c, DB, st);
+    default: return master ? launch_faces<double, float>(in, V, L, c, DB, st) : launch_faces<float, float>(in, V, L, c, DB, st);
+    }
+}
+
+hipError_t launch_msd_update(Prec prec, const StageArgs &a, hipStream_t st)
+{
+    switch (prec) {
+    case P_F64: return launch_update<double, double, double>(a, st);
+    case P_F32: return launch_update<float, float, float>(a, st);
+    default:
+        if (a.stage == 1) return launch_update<double, float, double>(a, st);
+        return launch_update<float, float, double>(a, st);
+    }
+}
+
+hipError_t launch_msd_bound(Prec prec, const void *psin, const void *V, const void *const DB[3], const Layout &L,
+                            const Coeffs &c, double h2a, double *dev_out, hipStream_t st)
+{
+    hipError_t e = hipMemsetAsync(dev_out, 0, sizeof(double), st);
+    if (e != hipSuccess) return e;
+    int64_t maxf = 1;
+    for (int a = 0; a < L.dim; ++a) {
+        int64_t f = 1;
+        for (int b = 0; b < L.dim; ++b)
+            if (b != a) f *= (b == 0 ? L.nx : b == 1 ? L.ny : L.nz) + 1;
+        if (f > maxf) maxf = f;
+    }
+    dim3 grid((unsigned)((maxf + 255) / 256), (unsigned)L.dim, 2);
+    unsigned long long *o = (unsigned long long *)dev_out;
+    switch (prec) {
+    case P_F64:
+        hipLaunchKernelGGL((msd_bound_kernel<double, double>), grid, dim3(256), 0, st,
+                           Field<double, double>{(const C<double> *)psin, (const double *)V, L}, c, DB[0], DB[1], DB[2],
+                           h2a, o);
+        break;
+    case P_F32:
+        hipLaunchKernelGGL((msd_bound_kernel<float, float>), grid, dim3(256), 0, st,
+                           Field<float, float>{(const C<float> *)psin, (const float *)V, L}, c, DB[0], DB[1], DB[2],
+                           h2a, o);
+        break;
+    default:
+        hipLaunchKernelGGL((msd_bound_kernel<double, float>), grid, dim3(256), 0, st,
+                           Field<double, float>{(const C<double> *)psin, (const float *)V, L}, c, DB[0], DB[1], DB[2],
+                           h2a, o);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace nlse

@@ -105,14 +105,22 @@ static hipError_t launch_stage(nlse_ctx *c, int stage, double dt, int variant)
     a.stage = stage;
     a.variant = variant;
     a.stencil = c->stencil;
-    return c->p.ndim == 2 ? launch_stage2d(c->prec, a, c->stream) : launch_stage3d(c->prec, a, c->stream);
+    const bool msd = c->p.bc == NLSE_BC_MSD;
+    if (msd) {   // face values of this stage's input (Eq. msdbc_lap)
+        hipError_t e = launch_msd_faces(c->prec, stage == 1, a.in, c->V, c->L, a.c, c->DB, c->stream);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = c->p.ndim == 2 ? launch_stage2d(c->prec, a, c->stream) : launch_stage3d(c->prec, a, c->stream);
+    if (e != hipSuccess || !msd) return e;
+    return launch_msd_update(c->prec, a, c->stream);   // boundary nodes (Eq. msdbc_ut)
 }
 
 // 2D variants: [0, stage2d_variants()) are the stage kernels, the rest the
 // whole-step kernels (their 32-bit offsets need fields below 2^31 elements).
 static bool step2d_ok(const nlse_ctx *c)
 {
-    return c->p.ndim == 2 && c->stencil == NLSE_STENCIL_2SHOC && c->L.total < (int64_t(1) << 31);
+    return c->p.ndim == 2 && c->stencil == NLSE_STENCIL_2SHOC && c->p.bc == NLSE_BC_DIRICHLET &&
+           c->L.total < (int64_t(1) << 31);
 }
 
 static int variant_count(const nlse_ctx *c)
@@ -269,9 +277,7 @@ int nlse_create(nlse_ctx **out, const nlse_params *p)
     if (p->bc != NLSE_BC_DIRICHLET && p->bc != NLSE_BC_MSD) return fail(NLSE_E_INVAL, "unknown bc");
     if (p->prec != NLSE_F64 && p->prec != NLSE_F32 && p->prec != NLSE_F32_MIXED)
         return fail(NLSE_E_INVAL, "unknown precision");
-    if (p->bc == NLSE_BC_MSD && p->ndim != 1)
-        return fail(NLSE_E_UNSUPPORTED, "the MSD boundary is implemented in 1D only");
-    if (p->bc == NLSE_BC_MSD && p->n[0] < 4) return fail(NLSE_E_INVAL, "MSD needs n >= 4 intervals");
+    if (p->bc == NLSE_BC_MSD && p->ndim == 1 && p->n[0] < 4) return fail(NLSE_E_INVAL, "MSD needs n >= 4 intervals");
 
     nlse_ctx *c = new nlse_ctx();
     c->p = *p;
@@ -337,7 +343,9 @@ void nlse_destroy(nlse_ctx *c)
 int nlse_launches_per_step(const nlse_ctx *c)
 {
     if (!c) return fail(NLSE_E_INVAL, "NULL context");
-    return c->p.ndim == 1 ? 0 : whole_step(c, c->variant) ? 1 : 4;
+    if (c->p.ndim == 1) return 0;
+    if (whole_step(c, c->variant)) return 1;
+    return c->p.bc == NLSE_BC_MSD ? 12 : 4;   // MSD: face values, interior, boundary per stage
 }
 
 int nlse_sync(nlse_ctx *c)
@@ -431,7 +439,16 @@ int nlse_max_dt(nlse_ctx *c, double *out)
     const double h2a = c->p.h * c->p.h / c->p.a;
     const double lmin = h2a * mm[0], lmax = h2a * mm[1];
     double m = std::fmax(gmax[c->p.ndim - 1] - lmin, lmax - gmin[c->p.ndim - 1]);
-    if (c->p.bc == NLSE_BC_MSD) {
+    if (c->p.bc == NLSE_BC_MSD && c->p.ndim > 1) {
+        Coeffs co = base_coeffs(c->p);
+        const void *db[3] = {c->DB[0], c->DB[1], c->DB[2]};
+        HIPTRY(launch_msd_faces(c->prec, true, c->psi, c->V, c->L, co, c->DB, c->stream));
+        HIPTRY(launch_msd_bound(c->prec, c->psi, c->V, db, c->L, co, h2a, c->red + 2 * reduce_partials(), c->stream));
+        double B;
+        rc = read_scalars(c, &B, 1);
+        if (rc) return rc;
+        m = std::fmax(m, B);
+    } else if (c->p.bc == NLSE_BC_MSD) {
         double e[8][2];
         rc = host_edges_1d(c, e);
         if (rc) return rc;
@@ -462,8 +479,8 @@ int nlse_set_field(nlse_ctx *c, const void *psi, int on_device)
     if (c->p.ndim > 1) {
         HIPTRY(launch_master_to_stage(c->prec, c->psi, c->A, c->L, c->stream));
         HIPTRY(launch_master_to_stage(c->prec, c->psi, c->B, c->L, c->stream));
-        Coeffs co = base_coeffs(c->p);
-        HIPTRY(launch_boundary_d(c->prec, c->psi, c->V, c->L, co, c->DB, c->stream));
+        Coeffs co = base_coeffs(c->p);   // Dirichlet face values are constants; MSD ones follow each stage
+        if (c->p.bc == NLSE_BC_DIRICHLET) HIPTRY(launch_boundary_d(c->prec, c->psi, c->V, c->L, co, c->DB, c->stream));
     }
     c->have_field = true;
     double k;
@@ -559,6 +576,8 @@ int nlse_energy(nlse_ctx *c, double *out)
                               c->stream));
         HIPTRY(hipStreamSynchronize(c->stream));
     }
+    if (c->p.ndim > 1 && c->p.bc == NLSE_BC_MSD)   // face values of the current field (Eq. msdbc_lap)
+        HIPTRY(launch_msd_faces(c->prec, true, c->psi, c->V, c->L, co, c->DB, c->stream));
     const void *db[3] = {c->DB[0], c->DB[1], c->DB[2]};
     HIPTRY(launch_energy(c->prec, c->psi, c->V, db, c->L, co, c->red, c->red + 2 * reduce_partials(), c->stream));
     double e;

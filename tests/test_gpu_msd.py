@@ -1,0 +1,155 @@
+"""GPU parity of the modulus-squared Dirichlet (MSD) boundary in 2D and 3D against the oracle.
+
+Under MSD (Sec. 3.2, Eqs. msdbc_lap, msdbc_ut; b-1 the closest interior node, the diagonal one on
+edges and corners) every RK4 stage runs the face-value launch, the interior stage kernel and the
+boundary update.  Tolerances as for Dirichlet: relative L2 over all nodes <= 1e-12 (FP64) and
+<= 1e-4 (FP32, mixed) after the whole run.  Sizes span several 64-column tiles with ragged tails.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import nlse_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-4, "mixed": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1109_1027_amd as P
+    P.load()
+    return P
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a, np.complex128) - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def vortex_case(n=150):
+    g = I.grid(2, n, -20.0, 20.0)
+    return g, I.background_vortices(g, pairs=2, seed=11)
+
+
+def ring_case(n=40):
+    g = I.grid(3, n, -8.0, 8.0)
+    return g, I.background_ring(g, ring_radius=3.0)
+
+
+def gpu_run(gpu, dim, n, h, psi, prec, nsteps, dt, variant=None, a=0.5, s=-1.0):
+    sol = gpu.Solver(dim, n, h, a, s, None, "msd", prec)
+    sol.set_field(psi.astype(sol.dtype))
+    if variant is not None:
+        sol.variant = variant
+    sol.step(nsteps, dt)
+    return sol.get_field(), sol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+def test_msd_2d_vortex_pairs(gpu, orc, prec):
+    g, psi = vortex_case()
+    P = orc.Problem(2, g.n, g.h, 0.5, -1.0, bc="msd")
+    dt = 0.5 * P.max_dt(psi)
+    say(f"[case] msd 2d vortices n={g.n} prec={prec} steps=40 dt={dt:.6g}")
+    out, sol = gpu_run(gpu, 2, g.n, g.h, psi, prec, 40, dt)
+    ref = P.rk4(psi, 40, dt)
+    e = rel(out, ref)
+    say(f"  rel L2 = {e:.3e}")
+    assert e <= TOL[prec]
+    # the boundary moved (the rule is live) yet kept its density
+    b = g.boundary_mask()
+    assert np.max(np.abs(ref[b] - psi[b])) > 1e-3
+    assert np.max(np.abs(np.abs(np.asarray(out, np.complex128)[b]) ** 2 - np.abs(psi[b]) ** 2)) < 1e-4
+    sol.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+def test_msd_3d_ring(gpu, orc, prec):
+    g, psi = ring_case()
+    P = orc.Problem(3, g.n, g.h, 0.5, -1.0, bc="msd")
+    dt = 0.5 * P.max_dt(psi)
+    say(f"[case] msd 3d ring n={g.n} prec={prec} steps=10 dt={dt:.6g}")
+    out, sol = gpu_run(gpu, 3, g.n, g.h, psi, prec, 10, dt)
+    ref = P.rk4(psi, 10, dt)
+    e = rel(out, ref)
+    say(f"  rel L2 = {e:.3e}")
+    assert e <= TOL[prec]
+    sol.close()
+
+
+def test_msd_2d_non_square_dark_plane(gpu, orc):
+    """Non-square grid (nx = 64, ny = 16), steep density at the x = lo face."""
+    n, psi = I.dark_plane(2, 0.25, width=4.0)
+    P = orc.Problem(2, n, 0.25, 0.5, -1.0, bc="msd")
+    nst, dt = orc.steps_for(1.0, P.max_dt(psi))
+    say(f"[case] msd 2d dark plane n={n} steps={nst}")
+    out, sol = gpu_run(gpu, 2, n, 0.25, psi, "f64", nst, dt)
+    ref = P.rk4(psi, nst, dt)
+    assert rel(out, ref) <= 1e-12
+    _, exact = I.dark_plane(2, 0.25, t=1.0, width=4.0)
+    assert rel(out, exact) < 1e-4   # the oracle's fourth-order error level at this h
+    sol.close()
+
+
+def test_msd_3d_non_cubic(gpu, orc):
+    n, psi = I.dark_plane(3, 0.25, width=1.5)   # 64 x 6 x 6 intervals
+    P = orc.Problem(3, n, 0.25, 0.5, -1.0, bc="msd")
+    dt = 0.5 * P.max_dt(psi)
+    say(f"[case] msd 3d dark plane n={n}")
+    out, sol = gpu_run(gpu, 3, n, 0.25, psi, "f64", 30, dt)
+    assert rel(out, P.rk4(psi, 30, dt)) <= 1e-12
+    sol.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_msd_variants_bit_identical(gpu, dim):
+    g, psi = vortex_case(130) if dim == 2 else ring_case(36)
+    sol = gpu.Solver(dim, g.n, g.h, 0.5, -1.0, None, "msd", "f64")
+    nv = sol.variant_count()
+    assert nv == (3 if dim == 2 else 4)   # no whole-step kernel under MSD
+    sol.set_field(psi)
+    dt = 0.4 * sol.max_dt()
+    sol.close()
+    outs = []
+    for v in range(nv):
+        say(f"[case] msd {dim}d variant {v}")
+        out, s2 = gpu_run(gpu, dim, g.n, g.h, psi, "f64", 5, dt, variant=v)
+        assert s2.launches_per_step() == 12
+        outs.append(out)
+        s2.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_msd_bound_energy_mass(gpu, orc, dim):
+    """The bound's boundary term, the energy (with the MSD step-1 face values of the current
+    field) and the mass against the oracle."""
+    g, psi = vortex_case(100) if dim == 2 else ring_case(30)
+    P = orc.Problem(dim, g.n, g.h, 0.5, -1.0, bc="msd")
+    say(f"[case] msd {dim}d bound/energy/mass n={g.n}")
+    sol = gpu.Solver(dim, g.n, g.h, 0.5, -1.0, None, "msd", "f64")
+    sol.set_field(psi)
+    k, aux = P.max_dt(psi, return_aux=True)
+    assert aux[2] > 0
+    assert sol.max_dt() == pytest.approx(k, rel=1e-12)
+    assert sol.energy() == pytest.approx(P.energy(psi), rel=1e-12)
+    assert sol.mass() == pytest.approx(P.mass(psi), rel=1e-13)
+    sol.close()
+
+
+def test_msd_2d_batch_rejected(gpu):
+    g, psi = vortex_case(64)
+    spec = I.ProblemSpec("v", g, 0.5, -1.0, None, psi, "msd")
+    with pytest.raises(gpu.NLSEError) as e:
+        gpu.Batch([spec], prec="f32")
+    assert e.value.code == -6

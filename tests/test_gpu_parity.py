@@ -227,8 +227,8 @@ def test_invalid_params(gpu):
         gpu.Solver(2, 10, 0.1, -1.0, 1.0)
     assert e.value.code == -1
     with pytest.raises(gpu.NLSEError) as e:
-        gpu.Solver(2, 10, 0.1, 1.0, 1.0, bc="msd")
-    assert e.value.code == -6
+        gpu.Solver(1, 3, 0.1, 1.0, 1.0, bc="msd")   # the 1D MSD rule reads nodes b..b-3
+    assert e.value.code == -1
 
 
 def test_checkpoint_resume_bitwise(gpu):
