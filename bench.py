@@ -40,6 +40,8 @@ WHOLE_STEP_BYTES = {"f64": 40, "f32": 20, "mixed": 36}
 # real flops of one RK4 step per interior point (FMA = 2): 4 x 41 for the two step-1
 # differences, step 2 and F, plus 26 for the K_tot and Psi updates
 FLOPS_PER_POINT_STEP = 190
+# ... and in 1D: 4 x 27 (one step-1 difference 8, step 2 8, F 11) + 26
+FLOPS_PER_POINT_STEP_1D = 134
 VECTOR_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "mixed": 157.3}
 
 METRIC = "2SHOC-RK4 Gpt·steps/s + % HBM peak; coarse+learned vs plain fine at equal L2 err"
@@ -220,7 +222,11 @@ def bench_batch(P, I, steps=1000):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     gpts = (pts1 + pts2) * steps / (ms * 1e-3) / 1e9
-    hbm = 152 * pts2 * steps / (ms * 1e-3) / 1e9
+    flops = (FLOPS_PER_POINT_STEP * pts2 + FLOPS_PER_POINT_STEP_1D * pts1) * steps
+    tflops = flops / (ms * 1e-3) / 1e12
+    # HBM: a 2D instance reads Psi^n and V and writes Psi^{n+1} per step (whole-step kernel);
+    # a 1D instance reads and writes its field once per launch (it lives on chip in between)
+    hbm = WHOLE_STEP_BYTES["f32"] * pts2 * steps / (ms * 1e-3) / 1e9
     b.close()
     print(f"[bench] batch: {gpts:.2f} Gpt*steps/s over {len(specs)} instances, {ms:.1f} ms for {steps} steps",
           file=sys.stderr, flush=True)
@@ -228,10 +234,38 @@ def bench_batch(P, I, steps=1000):
                         "at 256^2 (omega in [0.02, 0.1]), complex64, one persistent graph launch",
             "instances": len(specs), "steps": steps, "interior_point_steps": (pts1 + pts2) * steps,
             "value": gpts, "unit": "Gpt·steps/s", "ms": ms, "tile_variant": variant,
-            "roofline": {"bound": "hbm (2D instances; 1D instances run on chip)",
-                         "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm / HBM_PEAK_GBS,
-                         "traffic": None, "kernel": "nlse::batch_kernel",
-                         "note": "achieved counts only the 2D instances' algorithmic bytes (152 B/point-step)"}}
+            "roofline": {"bound": "alu", "achieved": tflops, "peak": VECTOR_PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                         "frac": tflops / VECTOR_PEAK_TFLOPS["f32"], "traffic": None,
+                         "kernel": "nlse::batch2d_kernel + nlse::batch1d_kernel (one graph launch)",
+                         "algorithmic_flops": flops,
+                         "flops_per_point_step": {"2d": FLOPS_PER_POINT_STEP, "1d": FLOPS_PER_POINT_STEP_1D},
+                         "attainable_peak_without_packed_fp32": VECTOR_PEAK_TFLOPS["f64"],
+                         "hbm_gbs_algorithmic": hbm, "hbm_frac_algorithmic": hbm / HBM_PEAK_GBS}}
+
+
+def bench_msd(P, I, args, res, npts):
+    """2D MSD boundary (Sec. 3.2, extended to 2D): vortex-antivortex pairs in a uniform background,
+    V = 0, on the 2049^2 grid; stage kernels plus the two boundary launches per stage, against the
+    Dirichlet stage kernels of the same tile variant."""
+    g = I.grid(2, args.n, -80.0, 80.0)
+    spec = I.ProblemSpec("msd2d", g, 0.5, -1.0, None, I.background_vortices(g, pairs=4, seed=3), "msd")
+    out = {"workload": f"2D NLSE with the MSD boundary, {args.n + 1}^2 nodes, a=0.5 s=-1 V=0 on [-80,80]^2, "
+                       "4 vortex-antivortex pairs in a uniform background + 1e-3 noise",
+           "interior_points": npts}
+    steps = max(args.steps // 4, 1)
+    for prec in ("f64", "f32"):
+        if prec not in res:
+            continue
+        sv = res[prec]["stage_kernels"]["roofline"]["tile_variant"]
+        ms, _, launches, dt, _, _ = time_solver(P, spec, prec, steps, 10, variant=sv)
+        gpts = npts * steps / (ms * 1e-3) / 1e9
+        ref = res[prec]["stage_kernels"]["ms_per_step"]
+        out[prec] = {"value": gpts, "unit": "Gpt·steps/s", "ms_per_step": ms / steps, "dt": dt,
+                     "launches_per_step": launches // steps, "tile_variant": sv,
+                     "dirichlet_stage_ms_per_step": ref, "boundary_overhead": ms / steps / ref - 1.0}
+        print(f"[bench] MSD 2D {prec} (stage kernels + boundary launches): {gpts:.2f} Gpt*steps/s, "
+              f"{100 * out[prec]['boundary_overhead']:.1f}% over Dirichlet", file=sys.stderr, flush=True)
+    return out
 
 
 def bench_learned(P, seed=9000):
@@ -272,6 +306,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=1000, help="steps of the batched workload (0: skip)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-corrector comparison")
     ap.add_argument("--no-stencils", action="store_true", help="skip the 2SHOC / non-compact / CD comparison")
+    ap.add_argument("--no-msd", action="store_true", help="skip the 2D MSD-boundary measurement")
     ap.add_argument("--variant2d", default="", help="force 2D kernel variants per precision, e.g. f64:6,f32:3 "
                                                     "(default: the library's autotuner)")
     ap.add_argument("--stage-variant", default="", help="force the stage-kernel comparison variants, e.g. f64:1")
@@ -380,6 +415,8 @@ def main():
         print(f"[bench] copy ceiling failed: {e}", file=sys.stderr)
     if stencils:
         out["stencils_stage_kernels"] = stencils
+    if not args.no_msd:
+        out["msd2d"] = bench_msd(P, I, args, res, npts)
     if args.n3d > 0:
         out["gp3d"] = bench_3d(P, I, args)
     if args.batch_steps > 0:

@@ -31,20 +31,29 @@ namespace {
 template <typename T, typename U> struct same_m { static constexpr bool v = false; };
 template <typename T> struct same_m<T, T> { static constexpr bool v = true; };
 
+// A node (x, y, z); the axis is selected by value, never by a dynamic array index,
+// so nothing lands in scratch memory.
 struct Node {
-    int64_t c[3];
+    int x, y, z;
+    __device__ __forceinline__ int at(int a) const { return a == 0 ? x : a == 1 ? y : z; }
+    __device__ __forceinline__ void set(int a, int v)
+    {
+        if (a == 0) x = v;
+        else if (a == 1) y = v;
+        else z = v;
+    }
 };
 
-__device__ __forceinline__ int64_t ext(const Layout &L, int a) { return a == 0 ? L.nx : a == 1 ? L.ny : L.nz; }
+__device__ __forceinline__ int ext(const Layout &L, int a) { return (int)(a == 0 ? L.nx : a == 1 ? L.ny : L.nz); }
 
 __device__ __forceinline__ bool on_bnd(const Layout &L, const Node &q, int a)
 {
-    return a < L.dim && (q.c[a] == 0 || q.c[a] == ext(L, a));
+    return a < L.dim && (q.at(a) == 0 || q.at(a) == ext(L, a));
 }
 
 __device__ __forceinline__ Node step(Node q, int a, int d)
 {
-    q.c[a] += d;
+    q.set(a, q.at(a) + d);
     return q;
 }
 
@@ -53,8 +62,8 @@ __device__ __forceinline__ Node step(Node q, int a, int d)
 __device__ __forceinline__ int64_t face_index(const Layout &L, int a, const Node &q)
 {
     const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
-    int64_t fi = q.c[t1];
-    if (t2 < L.dim) fi += q.c[t2] * (ext(L, t1) + 1);
+    int64_t fi = q.at(t1);
+    if (t2 < L.dim) fi += (int64_t)q.at(t2) * (ext(L, t1) + 1);
     return fi;
 }
 
@@ -70,21 +79,22 @@ __device__ __forceinline__ int64_t face_size(const Layout &L, int a)
 __device__ __forceinline__ Node face_node(const Layout &L, int a, int side, int64_t fi)
 {
     const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
-    Node q;
-    q.c[0] = q.c[1] = q.c[2] = 0;
-    q.c[a] = side ? ext(L, a) : 0;
+    Node q{0, 0, 0};
+    q.set(a, side ? ext(L, a) : 0);
     const int64_t m1 = ext(L, t1) + 1;
-    q.c[t1] = fi % m1;
-    if (t2 < L.dim) q.c[t2] = fi / m1;
+    q.set(t1, (int)(fi % m1));
+    if (t2 < L.dim) q.set(t2, (int)(fi / m1));
     return q;
 }
 
 // b-1 of the MSD rule: one step inward along every boundary axis of b.
 __device__ __forceinline__ Node inner(const Layout &L, Node b)
 {
-    for (int a = 0; a < L.dim; ++a) {
-        if (b.c[a] == 0) b.c[a] = 1;
-        else if (b.c[a] == ext(L, a)) b.c[a] = ext(L, a) - 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a >= L.dim) break;
+        if (b.at(a) == 0) b.set(a, 1);
+        else if (b.at(a) == ext(L, a)) b.set(a, ext(L, a) - 1);
     }
     return b;
 }
@@ -94,8 +104,8 @@ struct Field {
     const C<IN> *in;
     const R *V;
     Layout L;
-    __device__ __forceinline__ C<R> psi(const Node &q) const { return cvt<R, IN>(in[L.idx(q.c[0], q.c[1], q.c[2])]); }
-    __device__ __forceinline__ R pot(const Node &q) const { return V ? V[L.idx(q.c[0], q.c[1], q.c[2])] : R(0); }
+    __device__ __forceinline__ C<R> psi(const Node &q) const { return cvt<R, IN>(in[L.idx(q.x, q.y, q.z)]); }
+    __device__ __forceinline__ R pot(const Node &q) const { return V ? V[L.idx(q.x, q.y, q.z)] : R(0); }
     // delta_a^2 Psi at q (q +- e_a inside the grid)
     __device__ __forceinline__ C<R> d2a(const Node &q, int a, R ih2) const
     {
@@ -107,7 +117,7 @@ struct Field {
 template <typename R>
 __device__ __forceinline__ C<R> face_value(const Layout &L, const C<R> *const DB[3], int a, const Node &r)
 {
-    const int side = r.c[a] == 0 ? 0 : 1;
+    const int side = r.at(a) == 0 ? 0 : 1;
     return DB[a][side * face_size(L, a) + face_index(L, a, r)];
 }
 
@@ -118,11 +128,14 @@ __device__ C<R> interior_F(const Field<IN, R> &f, const C<R> *const DB[3], const
 {
     const R ih2 = (R)cf.ih2, c76 = (R)cf.c76, c112 = (R)cf.c112;
     C<R> dc[3], dl[3], dr[3];
-    for (int a = 0; a < f.L.dim; ++a) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        dc[a] = dl[a] = dr[a] = czero<R>();
+        if (a >= f.L.dim) continue;
         dc[a] = f.d2a(q, a, ih2);
         const Node lo = step(q, a, -1), hi = step(q, a, 1);
-        dl[a] = lo.c[a] == 0 ? face_value<R>(f.L, DB, a, lo) : f.d2a(lo, a, ih2);
-        dr[a] = hi.c[a] == ext(f.L, a) ? face_value<R>(f.L, DB, a, hi) : f.d2a(hi, a, ih2);
+        dl[a] = lo.at(a) == 0 ? face_value<R>(f.L, DB, a, lo) : f.d2a(lo, a, ih2);
+        dr[a] = hi.at(a) == ext(f.L, a) ? face_value<R>(f.L, DB, a, hi) : f.d2a(hi, a, ih2);
     }
     C<R> lap;
     if (f.L.dim == 2) {
@@ -156,19 +169,23 @@ __global__ void msd_face_kernel(Field<IN, R> f, Coeffs cf, C<R> *DBx, C<R> *DBy,
     const int64_t fi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (fi >= face_size(L, a)) return;
     const Node b = face_node(L, a, side, fi);
-    for (int t = 0; t < L.dim; ++t)
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
         if (t != a && on_bnd(L, b, t)) return;   // edge / corner: never read by the stage kernels
     const R ih2 = (R)cf.ih2, s = (R)cf.s;
     const Node q = step(b, a, side ? -1 : 1);
     const C<R> ub = f.psi(b), uq = f.psi(q);
     C<R> Dq = czero<R>();   // the full step-1 value at b-1 (Eqs. 2d2shocs1, 3d2shocs)
-    for (int t = 0; t < L.dim; ++t) Dq = cadd<R>(Dq, f.d2a(q, t, ih2));
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        if (t < L.dim) Dq = cadd<R>(Dq, f.d2a(q, t, ih2));
     const R den = uq.x * uq.x + uq.y * uq.y;
     const R ratio = den != R(0) ? (Dq.x * uq.x + Dq.y * uq.y) / den : R(0);
     const R fac = ratio + (nonlin<R>(uq, f.pot(q), s) - nonlin<R>(ub, f.pot(b), s)) * (R)cf.ia;
     C<R> Db = mk<R>(fac * ub.x, fac * ub.y);   // Lap_b
-    for (int t = 0; t < L.dim; ++t)
-        if (t != a) Db = csub<R>(Db, f.d2a(b, t, ih2));
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        if (t < L.dim && t != a) Db = csub<R>(Db, f.d2a(b, t, ih2));
     C<R> *dst = a == 0 ? DBx : a == 1 ? DBy : DBz;
     dst[side * face_size(L, a) + fi] = Db;
 }
@@ -196,8 +213,9 @@ static hipError_t launch_faces(const void *in, const void *V, const Layout &L, c
 // Every boundary node once: the face of the lowest axis on which it lies.
 __device__ __forceinline__ bool owner(const Layout &L, const Node &b, int a)
 {
-    for (int t = 0; t < a; ++t)
-        if (on_bnd(L, b, t)) return false;
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        if (t < a && on_bnd(L, b, t)) return false;
     return true;
 }
 
@@ -216,7 +234,7 @@ __global__ void msd_update_kernel(Field<IN, R> f, StageArgs A)
     const C<R> uq = f.psi(q), ub = f.psi(b);
     const R w = phase_rate<R>(interior_F<IN, R>(f, DB, A.c, q), uq);
     const C<R> F = mk<R>(-w * ub.y, w * ub.x);
-    const int64_t p = L.idx(b.c[0], b.c[1], b.c[2]);
+    const int64_t p = L.idx(b.x, b.y, b.z);
     const R ck = (R)A.c.ck;
     C<M> *psin = (C<M> *)A.psin;
     C<R> *K = (C<R> *)A.K;
