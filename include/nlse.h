@@ -148,10 +148,10 @@ const char *nlse_last_error(void);
 int nlse_launches_per_step(const nlse_ctx *c);
 
 /* Kernel variants.  2D: 0-2 are the stage kernels (one launch per RK4 stage, tiles of
- * 64 columns x 8, 4 or 16 rows per wave); 3-8 the whole-step kernels (one launch per RK4
+ * 64 columns x 8, 4 or 16 rows per wave); 3-9 the whole-step kernels (one launch per RK4
  * step, Sec. 3.1 with all four stages fused; a wave walks a 64-column strip down a segment
- * of 29, 20, 38, 56, 11 or 47 rows; offered under Dirichlet when the padded field has fewer
- * than 2^31 elements).
+ * of 29, 20, 38, 56, 11, 47 or 29 rows, the last with two rows of Psi^n in flight instead
+ * of one; offered under Dirichlet when the padded field has fewer than 2^31 elements).
  * 3D: stage kernels with 64 x 4 or 64 x 8 column tiles marching 16, 32 or 64 planes.
  * Every variant computes bit-identical fields; they differ only in speed.  1D contexts
  * have one. */

@@ -1,6 +1,7 @@
 // Auxiliary kernels: boundary-face closure values, field conversion, and the
 // deterministic FP64 reductions (mass, energy, extrema of s|Psi|^2 - V).
 #include "kernels.h"
+#include "point.h"
 
 namespace nlse {
 
@@ -46,8 +47,7 @@ __global__ void boundary_d_kernel(const C<M> *psi, const R *V, Layout L, Coeffs 
     const int64_t p = L.idx(co[0], co[1], co[2]);
     const C<M> u = psi[p];
     const M Vq = V ? (M)V[p] : M(0);
-    const M N = (M)c.s * (u.x * u.x + u.y * u.y) - Vq;
-    M rx = -N * (M)c.ia * u.x, ry = -N * (M)c.ia * u.y;
+    C<M> acc = dirichlet_lapb<M>(u, Vq, (M)c.s, (M)c.ia);
     const int tang[2] = {t1, t2};
     for (int k = 0; k < 2; ++k) {
         const int b = tang[k];
@@ -57,11 +57,10 @@ __global__ void boundary_d_kernel(const C<M> *psi, const R *V, Layout L, Coeffs 
         cp[b] += 1;
         cm[b] -= 1;
         const C<M> up = psi[L.idx(cp[0], cp[1], cp[2])], um = psi[L.idx(cm[0], cm[1], cm[2])];
-        rx -= ih2 * ((up.x - M(2) * u.x) + um.x);
-        ry -= ih2 * ((up.y - M(2) * u.y) + um.y);
+        acc = csub<M>(acc, d2<M>(um, u, up, ih2));
     }
     C<R> *dst = axis == 0 ? DBx : axis == 1 ? DBy : DBz;
-    dst[side * m1 * m2 + i] = mk<R>((R)rx, (R)ry);
+    dst[side * m1 * m2 + i] = cvt<R, M>(acc);
 }
 
 template <typename R, typename M>

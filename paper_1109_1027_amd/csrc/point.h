@@ -80,6 +80,18 @@ __device__ __forceinline__ C<R> rhs(C<R> lap, C<R> u, R v, R a, R s)
     return mk<R>(-zy, zx);
 }
 
+// Dirichlet closure of step 1 on a boundary node (Sec. 3.2, Eq. dbc_lap):
+// Lap_b = -(s |Psi_b|^2 - V_b) Psi_b / a, with ia = 1/a.  The per-axis kernels read
+// D^a_b = Lap_b - (second differences along the face) on a face node normal to a;
+// every kernel forms that value with these helpers in the master precision.
+template <typename M>
+__device__ __forceinline__ C<M> dirichlet_lapb(C<M> u, M v, M s, M ia)
+{
+#pragma clang fp contract(off)
+    const M f = -(nonlin<M>(u, v, s) * ia);
+    return mk<M>(f * u.x, f * u.y);
+}
+
 // K_tot accumulation of stages 2 and 3: K + 2F (2F is exact).
 template <typename R>
 __device__ __forceinline__ C<R> kacc(C<R> k, C<R> F)

@@ -33,7 +33,7 @@ namespace {
 
 constexpr int NW = 4;      // waves per block (independent)
 
-template <typename R, typename M, int Q>
+template <typename R, typename M, int Q, int PD>
 __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs A, int strips, int waves)
 {
     constexpr int FR = wave2d::face_rows<Q>();
@@ -44,10 +44,10 @@ __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs A, int strips, i
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int w = (int)xcd_remap(blockIdx.x, gridDim.x) * NW + wv;
     if (w >= waves) return;                 // whole waves only; the kernel has no barriers
-    wave2d::step2d_wave<R, M, Q>(A, w % strips, w / strips, threadIdx.x & 63, sdx[wv], sdy[wv]);
+    wave2d::step2d_wave<R, M, Q, PD>(A, w % strips, w / strips, threadIdx.x & 63, sdx[wv], sdy[wv]);
 }
 
-template <typename R, typename M, int Q>
+template <typename R, typename M, int Q, int PD = 1>
 hipError_t launch_q(const Step2DArgs &a, hipStream_t st)
 {
     if (a.L.total >= (int64_t(1) << 31)) return hipErrorInvalidValue;   // 32-bit offsets
@@ -55,7 +55,7 @@ hipError_t launch_q(const Step2DArgs &a, hipStream_t st)
     const int segs = wave2d::segments<Q>(a.L.ny);
     const int waves = strips * segs;
     const int blocks = (waves + NW - 1) / NW;
-    hipLaunchKernelGGL((step2d_kernel<R, M, Q>), dim3(blocks), dim3(64 * NW), 0, st, a, strips, waves);
+    hipLaunchKernelGGL((step2d_kernel<R, M, Q, PD>), dim3(blocks), dim3(64 * NW), 0, st, a, strips, waves);
     return hipGetLastError();
 }
 
@@ -69,13 +69,14 @@ hipError_t launch_v(const Step2DArgs &a, hipStream_t st)
     case 3: return launch_q<R, M, 8>(a, st);    // 56
     case 4: return launch_q<R, M, 3>(a, st);    // 11 (small grids: more, shorter waves)
     case 5: return launch_q<R, M, 7>(a, st);    // 47
+    case 6: return launch_q<R, M, 5, 2>(a, st);  // 29, two rows of Psi^n in flight (pays off in mixed)
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-int step2d_variants() { return 6; }
+int step2d_variants() { return 7; }
 
 hipError_t launch_step2d(Prec prec, const Step2DArgs &a, hipStream_t st)
 {

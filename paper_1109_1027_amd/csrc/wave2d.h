@@ -25,7 +25,7 @@ template <int Q> __host__ __device__ inline int segments(int64_t ny) { return (i
 // rows), sdy: [2][64] (D^y on the faces y = 0 and y = ny for its columns);
 // wave-private LDS, rewritten by every call.  strip < strips(nx) and
 // seg < segments<Q>(ny), wave-uniform; the field has < 2^31 elements.
-template <typename R, typename M, int Q>
+template <typename R, typename M, int Q, int PD = 1>
 __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int seg, int lane,
                                             C<R> (*sdx)[face_rows<Q>()], C<R> (*sdy)[64])
 {
@@ -90,9 +90,11 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
         pv = pin[o];
         vv = V[o];
     };
-    C<M> pf;
-    R vf;
-    load_row(jb, pf, vf);
+    // PD rows of Psi^n and V in flight ahead of the row being consumed
+    C<M> pf[PD];
+    R vf[PD];
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_row(jb + d, pf[d], vf[d]);
 
 #pragma unroll 1
     for (int g = 0; g < Q; ++g) {
@@ -100,9 +102,14 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
         for (int p = 0; p < 9; ++p) {
             const int t = 9 * g + p;
             const int j = jb + t;
-            P[p] = pf;
-            Vq[p] = vf;
-            load_row(j + 1, pf, vf);        // prefetch
+            P[p] = pf[0];
+            Vq[p] = vf[0];
+#pragma unroll
+            for (int d = 0; d + 1 < PD; ++d) {
+                pf[d] = pf[d + 1];
+                vf[d] = vf[d + 1];
+            }
+            load_row(j + PD, pf[PD - 1], vf[PD - 1]);   // prefetch
             const int q0 = p % 3, q1 = (p + 1) % 3, q2 = (p + 2) % 3;   // rows m, m-2, m-1
             C<R> in = cvt<R, M>(P[p]);
 #pragma unroll
