@@ -37,6 +37,9 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_POINT_STEP = {"f64": 304, "f32": 152, "mixed": 192}
 # ... and of the whole-step kernel: Psi^n and V read, Psi^{n+1} written
 WHOLE_STEP_BYTES = {"f64": 40, "f32": 20, "mixed": 36}
+# ... and of the 3D two-stage kernels (two launches per step): stages 1+2 read Psi^n, V and write
+# K, B; stages 3+4 read B, K, Psi^n, V and write Psi^{n+1} (f32: 28 + 36; mixed 36 + 52; f64 56 + 72)
+PAIR3D_BYTES = {"f64": 128, "f32": 64, "mixed": 88}
 # real flops of one RK4 step per interior point (FMA = 2): 4 x 41 for the two step-1
 # differences, step 2 and F, plus 26 for the K_tot and Psi updates
 FLOPS_PER_POINT_STEP = 190
@@ -188,17 +191,35 @@ def bench_3d(P, I, args):
     for prec in args.precs3d.split(","):
         ms, wall, launches, dt, mass, variant = time_solver(P, spec, prec, args.steps3d, 5)
         gpts = npts * args.steps3d / (ms * 1e-3) / 1e9
-        per_launch_bytes = BYTES_PER_POINT_STEP[prec] * npts / 4
+        lps = launches // args.steps3d
+        pairs = lps == 2   # the autotuner picked the two-stage kernels
+        step_bytes = (PAIR3D_BYTES if pairs else BYTES_PER_POINT_STEP)[prec] * npts
+        per_launch_bytes = step_bytes / lps
         achieved = per_launch_bytes / (ms * 1e-3 / launches) / 1e9
+        stage_eq = BYTES_PER_POINT_STEP[prec] * npts * args.steps3d / (ms * 1e-3) / 1e9
         res[prec] = {"value": gpts, "unit": "Gpt·steps/s", "ms_per_step": ms / args.steps3d, "dt": dt,
+                     "launches_per_step": lps,
                      "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                   "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                                  "kernel": "nlse::stage3d_kernel",
+                                  "kernel": "nlse::pair3d_kernel" if pairs else "nlse::stage3d_kernel",
                                   "algorithmic_bytes_per_launch": per_launch_bytes,
+                                  "stage_equivalent_gbs": stage_eq, "stage_equivalent_frac": stage_eq / HBM_PEAK_GBS,
                                   "avg_launch_us": ms * 1e3 / launches, "tile_variant": variant}}
-        print(f"[bench] 3D {prec}: {gpts:.2f} Gpt*steps/s, {ms / args.steps3d:.3f} ms/step, "
-              f"{achieved:.0f} GB/s algorithmic ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)",
-              file=sys.stderr, flush=True)
+        print(f"[bench] 3D {prec}: {gpts:.2f} Gpt*steps/s, {ms / args.steps3d:.3f} ms/step, {lps} launches/step, "
+              f"{achieved:.0f} GB/s algorithmic ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak; "
+              f"{stage_eq:.0f} GB/s in the four-launch form's bytes)", file=sys.stderr, flush=True)
+        if pairs:   # the four-launch stage kernels on the same workload, for comparison
+            sv = min(range(4), key=lambda v: time_solver(P, spec, prec, 20, 2, variant=v)[0])
+            ms_s, _, launches_s, _, _, _ = time_solver(P, spec, prec, args.steps3d, 5, variant=sv)
+            ach_s = BYTES_PER_POINT_STEP[prec] * npts * args.steps3d / (ms_s * 1e-3) / 1e9
+            res[prec]["stage_kernels"] = {"value": npts * args.steps3d / (ms_s * 1e-3) / 1e9,
+                                          "ms_per_step": ms_s / args.steps3d, "tile_variant": sv,
+                                          "roofline": {"bound": "hbm", "achieved": ach_s, "peak": HBM_PEAK_GBS,
+                                                       "unit": "GB/s", "frac": ach_s / HBM_PEAK_GBS,
+                                                       "kernel": "nlse::stage3d_kernel"}}
+            print(f"[bench] 3D {prec} stage kernels: {res[prec]['stage_kernels']['value']:.2f} Gpt*steps/s, "
+                  f"{ach_s:.0f} GB/s algorithmic ({100 * ach_s / HBM_PEAK_GBS:.1f}% of HBM peak)",
+                  file=sys.stderr, flush=True)
     return res
 
 

@@ -143,7 +143,8 @@ const char *nlse_last_error(void);
 
 /* Number of kernel launches one RK4 step enqueues for this context with its current
  * variant: 4 for the 2D/3D stage kernels (12 under MSD: face values and boundary update
- * around each stage), 1 for the 2D whole-step kernels (Dirichlet only); 1D contexts
+ * around each stage), 1 for the 2D whole-step kernels and 2 for the 3D two-stage kernels
+ * (Dirichlet only); 1D contexts
  * advance all steps in one launch and report 0.  For throughput accounting. */
 int nlse_launches_per_step(const nlse_ctx *c);
 
@@ -152,7 +153,9 @@ int nlse_launches_per_step(const nlse_ctx *c);
  * step, Sec. 3.1 with all four stages fused; a wave walks a 64-column strip down a segment
  * of 29, 20, 38, 56, 11, 47 or 29 rows, the last with two rows of Psi^n in flight instead
  * of one; offered under Dirichlet when the padded field has fewer than 2^31 elements).
- * 3D: stage kernels with 64 x 4 or 64 x 8 column tiles marching 16, 32 or 64 planes.
+ * 3D: 0-3 stage kernels with 64 x 4 or 64 x 8 column tiles marching 16, 32 or 64 planes;
+ * 4-6 (Dirichlet, fields below 2^31 elements) two launches per step, each fusing two stages
+ * (1+2, 3+4) on 64 x 16 or 64 x 8 column tiles marching 32 or 64 planes.
  * Every variant computes bit-identical fields; they differ only in speed.  1D contexts
  * have one. */
 int nlse_variant_count(const nlse_ctx *c);

@@ -28,7 +28,7 @@ struct nlse_ctx {
     nlse::Prec prec;
     size_t esR, esM, rR;        // bytes: stage complex, master complex, stage real
     void *psi = nullptr, *A = nullptr, *B = nullptr, *K = nullptr, *V = nullptr;
-    void *psi2 = nullptr;       // 2D: second master buffer of the whole-step kernel (swapped with psi)
+    void *psi2 = nullptr;       // second master buffer of the 2D whole-step and 3D pair kernels (swapped with psi)
     void *V0 = nullptr;         // 2D without potential: zeros, read by the whole-step kernel
     void *DB[3] = {nullptr, nullptr, nullptr};
     double *red = nullptr;      // reduction partials (2 * reduce_partials()) + result slots

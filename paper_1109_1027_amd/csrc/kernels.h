@@ -52,6 +52,25 @@ struct Step2DArgs {
 hipError_t launch_step2d(Prec prec, const Step2DArgs &a, hipStream_t st);
 int step2d_variants();
 
+// 3D step as two launches of two fused stages each (see step3d.hip): pair 1 reads
+// psin (Psi^n) and V and writes K and B (the stage-2 field); pair 2 reads B, K,
+// psin and V and writes Psi^{n+1} to psi_out, a different buffer whose boundary
+// nodes already hold the (fixed) Dirichlet values.
+struct Step3DArgs {
+    const void *psin;
+    void *psi_out;
+    void *K;
+    void *B;
+    const void *V;       // potential (real, stage type) or nullptr
+    const void *DB[3];   // boundary-face normal second differences (as in StageArgs)
+    Layout L;
+    Coeffs c;            // ck unused
+    double ck[4];        // k/2, k/2, k, k/6
+    int variant;
+};
+hipError_t launch_step3d(Prec prec, const Step3DArgs &a, hipStream_t st);
+int step3d_variants();
+
 // 1D persistent solver: one workgroup holds the whole field on chip and runs
 // nsteps RK4 steps in one launch.
 struct Solve1DArgs {

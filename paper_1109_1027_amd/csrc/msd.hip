@@ -141,11 +141,7 @@ __device__ C<R> interior_F(const Field<IN, R> &f, const C<R> *const DB[3], const
     if (f.L.dim == 2) {
         lap = lap2<R>(dc[0], dc[1], dl[0], dr[0], dl[1], dr[1], c76, c112);
     } else {
-#pragma clang fp contract(off)
-        const R ax = (dc[0].x + dc[1].x) + dc[2].x, ay = (dc[0].y + dc[1].y) + dc[2].y;
-        const R bx = ((dr[0].x + dl[0].x) + (dr[1].x + dl[1].x)) + (dr[2].x + dl[2].x);
-        const R by = ((dr[0].y + dl[0].y) + (dr[1].y + dl[1].y)) + (dr[2].y + dl[2].y);
-        lap = mk<R>(fmar(c76, ax, -(c112 * bx)), fmar(c76, ay, -(c112 * by)));
+        lap = lap3<R>(dc[0], dc[1], dc[2], dl[0], dr[0], dl[1], dr[1], dl[2], dr[2], c76, c112);
     }
     return rhs<R>(lap, f.psi(q), f.pot(q), (R)cf.a, (R)cf.s);
 }

@@ -32,6 +32,19 @@ __device__ __forceinline__ C<R> lap2(C<R> dx, C<R> dy, C<R> dxl, C<R> dxr, C<R> 
     return mk<R>(fmar(c76, ax, -(c112 * bx)), fmar(c76, ay, -(c112 * by)));
 }
 
+// Step 2 of the per-axis 3D form (Sec. 2.3, Eqs. 3d2shocMs1-2): (7/6)(D^x + D^y + D^z)
+// - (1/12)(sum of the six axis neighbours' D^a).
+template <typename R>
+__device__ __forceinline__ C<R> lap3(C<R> dx, C<R> dy, C<R> dz, C<R> dxl, C<R> dxr, C<R> dyd, C<R> dyu,
+                                     C<R> dzm, C<R> dzp, R c76, R c112)
+{
+#pragma clang fp contract(off)
+    const R ax = (dx.x + dy.x) + dz.x, ay = (dx.y + dy.y) + dz.y;
+    const R bx = ((dxr.x + dxl.x) + (dyu.x + dyd.x)) + (dzp.x + dzm.x);
+    const R by = ((dxr.y + dxl.y) + (dyu.y + dyd.y)) + (dzp.y + dzm.y);
+    return mk<R>(fmar(c76, ax, -(c112 * bx)), fmar(c76, ay, -(c112 * by)));
+}
+
 // Non-compact fourth-order second difference along one axis (Sec. 2.1, the stencil the
 // 2SHOC scheme is compared with): (-Psi_{+2} + 16 Psi_{+1} - 30 Psi_0 + 16 Psi_{-1} - Psi_{-2})
 // / (12 h^2), accumulated left to right; i12h2 = 1 / (12 h^2).

@@ -123,13 +123,47 @@ static bool step2d_ok(const nlse_ctx *c)
            c->L.total < (int64_t(1) << 31);
 }
 
+// 3D variants: [0, stage3d_variants()) the stage kernels, the rest the two-stage pairs
+// (Dirichlet, 32-bit offsets).
+static bool step3d_ok(const nlse_ctx *c)
+{
+    return c->p.ndim == 3 && c->p.bc == NLSE_BC_DIRICHLET && c->L.total < (int64_t(1) << 31);
+}
+
 static int variant_count(const nlse_ctx *c)
 {
     if (c->p.ndim == 2) return stage2d_variants() + (step2d_ok(c) ? step2d_variants() : 0);
-    return c->p.ndim == 3 ? stage3d_variants() : 1;
+    if (c->p.ndim == 3) return stage3d_variants() + (step3d_ok(c) ? step3d_variants() : 0);
+    return 1;
 }
 
-static bool whole_step(const nlse_ctx *c, int variant) { return c->p.ndim == 2 && variant >= stage2d_variants(); }
+// Variants that write Psi^{n+1} into the second master buffer (2D whole step, 3D pairs).
+static bool whole_step(const nlse_ctx *c, int variant)
+{
+    return (c->p.ndim == 2 && variant >= stage2d_variants()) || (c->p.ndim == 3 && variant >= stage3d_variants());
+}
+
+// One RK4 step of a 3D context as two launches of two fused stages: psi -> psi2, then swap.
+static hipError_t launch_pair_step(nlse_ctx *c, double dt, int variant)
+{
+    Step3DArgs a;
+    a.psin = c->psi;
+    a.psi_out = c->psi2;
+    a.K = c->K;
+    a.B = c->B;
+    a.V = c->V;
+    for (int d = 0; d < 3; ++d) a.DB[d] = c->DB[d];
+    a.L = c->L;
+    a.c = base_coeffs(c->p);
+    a.ck[0] = dt / 2.0;
+    a.ck[1] = dt / 2.0;
+    a.ck[2] = dt;
+    a.ck[3] = dt / 6.0;
+    a.variant = variant - stage3d_variants();
+    hipError_t e = launch_step3d(c->prec, a, c->stream);
+    if (e == hipSuccess) std::swap(c->psi, c->psi2);
+    return e;
+}
 
 // One RK4 step of a 2D context with a whole-step variant: psi -> psi2, then swap.
 static hipError_t launch_whole_step(nlse_ctx *c, double dt, int variant)
@@ -155,7 +189,7 @@ static hipError_t launch_whole_step(nlse_ctx *c, double dt, int variant)
 // One RK4 step with the given variant.
 static hipError_t launch_rk4_step(nlse_ctx *c, double dt, int variant)
 {
-    if (whole_step(c, variant)) return launch_whole_step(c, dt, variant);
+    if (whole_step(c, variant)) return c->p.ndim == 2 ? launch_whole_step(c, dt, variant) : launch_pair_step(c, dt, variant);
     for (int st = 1; st <= 4; ++st) {
         hipError_t e = launch_stage(c, st, dt, variant);
         if (e != hipSuccess) return e;
@@ -302,7 +336,7 @@ int nlse_create(nlse_ctx **out, const nlse_params *p)
         return NLSE_OK;
     };
     int rc = alloc(&c->psi, T * c->esM);
-    if (!rc && p->ndim == 2) rc = alloc(&c->psi2, T * c->esM);
+    if (!rc && (p->ndim == 2 || step3d_ok(c))) rc = alloc(&c->psi2, T * c->esM);
     if (!rc && p->ndim > 1) rc = alloc(&c->A, T * c->esR);
     if (!rc && p->ndim > 1) rc = alloc(&c->B, T * c->esR);
     if (!rc && p->ndim > 1) rc = alloc(&c->K, T * c->esR);
@@ -344,7 +378,7 @@ int nlse_launches_per_step(const nlse_ctx *c)
 {
     if (!c) return fail(NLSE_E_INVAL, "NULL context");
     if (c->p.ndim == 1) return 0;
-    if (whole_step(c, c->variant)) return 1;
+    if (whole_step(c, c->variant)) return c->p.ndim == 2 ? 1 : 2;
     return c->p.bc == NLSE_BC_MSD ? 12 : 4;   // MSD: face values, interior, boundary per stage
 }
 
@@ -474,7 +508,7 @@ int nlse_set_field(nlse_ctx *c, const void *psi, int on_device)
     if (!c || !psi) return fail(NLSE_E_INVAL, "nlse_set_field: NULL argument");
     int rc = copy_field(c, c->psi, (void *)psi, on_device, true);
     if (rc) return rc;
-    if (c->psi2)   // the whole-step kernel writes interiors only: give psi2 the boundary values
+    if (c->psi2)   // the whole-step / pair kernels write interiors only: give psi2 the boundary values
         HIPTRY(hipMemcpyAsync(c->psi2, c->psi, (size_t)c->L.total * c->esM, hipMemcpyDeviceToDevice, c->stream));
     if (c->p.ndim > 1) {
         HIPTRY(launch_master_to_stage(c->prec, c->psi, c->A, c->L, c->stream));

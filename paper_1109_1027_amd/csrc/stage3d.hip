@@ -26,6 +26,7 @@
 // launch_boundary_d; see stage2d.hip for why the per-axis and single-storage
 // forms then coincide.
 #include "kernels.h"
+#include "point.h"
 
 namespace nlse {
 
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
     const int cidx = y * px + x + ox;                    // own column, plane 0
 
     const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
-    const R ck = (R)A.c.ck, two = (R)2;
+    const R ck = (R)A.c.ck;
     const C<IN> *in = (const C<IN> *)A.in;
     const C<R> *DBx = (const C<R> *)A.DB[0];
     const C<R> *DBy = (const C<R> *)A.DB[1];
@@ -103,9 +104,7 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
     auto ldp = [&](int zz, int idx, bool ok) -> C<R> {   // Psi_in at plane zz (block-uniform bounds)
         return (ok && zz >= 0 && zz <= nz) ? cvt<R, IN>(in[zz * plane + idx]) : czero<R>();
     };
-    auto d2 = [&](const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> {
-        return cscale<R>(ih2, cadd<R>(csub<R>(p, cscale<R>(two, c)), m));
-    };
+    auto d2 = [&](const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> { return nlse::d2<R>(m, c, p, ih2); };
     auto dz_at = [&](int zz, const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> {
         if (!col_ok) return czero<R>();
         if (zz == 0) return DBz[y * (nx + 1) + x];
@@ -173,25 +172,19 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
         __syncthreads();
         if (upd_col) {
             const int p = z * plane + cidx;
-            const C<R> nb = cadd<R>(cadd<R>(cadd<R>(sdx[ty][tx + 2], sdx[ty][tx]), cadd<R>(sdy[ty + 2][tx], sdy[ty][tx])),
-                                    cadd<R>(dzp, dzm));
-            const C<R> lap = csub<R>(cscale<R>(c76, cadd<R>(cadd<R>(dx, dy), dz0)), cscale<R>(c112, nb));
+            const C<R> lap = lap3<R>(dx, dy, dz0, sdx[ty][tx], sdx[ty][tx + 2], sdy[ty][tx], sdy[ty + 2][tx], dzm, dzp,
+                                     c76, c112);
             const C<R> u = q[2];
-            const R nl = s * (u.x * u.x + u.y * u.y) - ops.vv;
-            const C<R> zz = cadd<R>(cscale<R>(a, lap), cscale<R>(nl, u));
-            const C<R> F = mk<R>(-zz.y, zz.x);
+            const C<R> F = rhs<R>(lap, u, ops.vv, a, s);
             if (STAGE == 1) {
                 const C<M> base = in_is_r ? cvt<M, R>(u) : ops.pn;
                 K[p] = F;
-                const C<R> inc = cscale<R>(ck, F);
-                out[p] = cvt<R, M>(mk<M>(base.x + (M)inc.x, base.y + (M)inc.y));
+                out[p] = cvt<R, M>(axpy_m<R, M>(base, ck, F));
             } else if (STAGE <= 3) {
-                K[p] = cadd<R>(ops.kt, cscale<R>(two, F));
-                const C<R> inc = cscale<R>(ck, F);
-                out[p] = cvt<R, M>(mk<M>(ops.pn.x + (M)inc.x, ops.pn.y + (M)inc.y));
+                K[p] = kacc<R>(ops.kt, F);
+                out[p] = cvt<R, M>(axpy_m<R, M>(ops.pn, ck, F));
             } else {
-                const C<R> inc = cscale<R>(ck, cadd<R>(ops.kt, F));
-                psin[p] = mk<M>(ops.pn.x + (M)inc.x, ops.pn.y + (M)inc.y);
+                psin[p] = axpy_m<R, M>(ops.pn, ck, cadd<R>(ops.kt, F));
             }
         }
         q[0] = q[1];
