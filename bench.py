@@ -188,8 +188,9 @@ def bench_3d(P, I, args):
     res = {"workload": f"3D Gross-Pitaevskii 2SHOC-RK4, {args.n3d + 1}^3 nodes, a=0.5 s=-1 omega=0.1 on "
                        "[-24,24]^3, Dirichlet 0, Thomas-Fermi cloud x vortex-ring phase",
            "interior_points": npts, "steps": args.steps3d}
+    force3d = parse_variants(args.variant3d)
     for prec in args.precs3d.split(","):
-        ms, wall, launches, dt, mass, variant = time_solver(P, spec, prec, args.steps3d, 5)
+        ms, wall, launches, dt, mass, variant = time_solver(P, spec, prec, args.steps3d, 5, variant=force3d.get(prec))
         gpts = npts * args.steps3d / (ms * 1e-3) / 1e9
         lps = launches // args.steps3d
         pairs = lps == 2   # the autotuner picked the two-stage kernels
@@ -200,7 +201,8 @@ def bench_3d(P, I, args):
         res[prec] = {"value": gpts, "unit": "Gpt·steps/s", "ms_per_step": ms / args.steps3d, "dt": dt,
                      "launches_per_step": lps,
                      "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                                  "frac": achieved / HBM_PEAK_GBS,
+                                  "traffic": measured_traffic("pair3d", prec, variant) if pairs else None,
                                   "kernel": "nlse::pair3d_kernel" if pairs else "nlse::stage3d_kernel",
                                   "algorithmic_bytes_per_launch": per_launch_bytes,
                                   "stage_equivalent_gbs": stage_eq, "stage_equivalent_frac": stage_eq / HBM_PEAK_GBS,
@@ -208,7 +210,7 @@ def bench_3d(P, I, args):
         print(f"[bench] 3D {prec}: {gpts:.2f} Gpt*steps/s, {ms / args.steps3d:.3f} ms/step, {lps} launches/step, "
               f"{achieved:.0f} GB/s algorithmic ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak; "
               f"{stage_eq:.0f} GB/s in the four-launch form's bytes)", file=sys.stderr, flush=True)
-        if pairs:   # the four-launch stage kernels on the same workload, for comparison
+        if pairs and not args.no_stage3d:   # the four-launch stage kernels on the same workload, for comparison
             sv = min(range(4), key=lambda v: time_solver(P, spec, prec, 20, 2, variant=v)[0])
             ms_s, _, launches_s, _, _, _ = time_solver(P, spec, prec, args.steps3d, 5, variant=sv)
             ach_s = BYTES_PER_POINT_STEP[prec] * npts * args.steps3d / (ms_s * 1e-3) / 1e9
@@ -331,6 +333,8 @@ def main():
     ap.add_argument("--variant2d", default="", help="force 2D kernel variants per precision, e.g. f64:6,f32:3 "
                                                     "(default: the library's autotuner)")
     ap.add_argument("--stage-variant", default="", help="force the stage-kernel comparison variants, e.g. f64:1")
+    ap.add_argument("--variant3d", default="", help="force 3D kernel variants per precision, e.g. f32:4,mixed:5")
+    ap.add_argument("--no-stage3d", action="store_true", help="skip the 3D stage-kernel comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "

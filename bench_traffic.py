@@ -1,10 +1,11 @@
 """Turn two rocprofv3 counter runs of bench.py into per-launch HBM traffic of a 2D kernel.
 
 Usage: python bench_traffic.py <step2d|stage2d> <variant2d> <stage_variant> <fetch_collection.csv> <write_collection.csv>
+       python bench_traffic.py pair3d <variant3d> - <fetch_collection.csv> <write_collection.csv>
        python bench_traffic.py valu <variant2d> <valu_counter_collection.csv>   (VALU issue of the whole-step kernel)
 
-<variant2d> and <stage_variant> are the per-precision kernel variants the counter runs of bench.py
-were given (--variant2d, --stage-variant), e.g. f64:6,f32:3,mixed:3.
+<variant2d>, <stage_variant> and <variant3d> are the per-precision kernel variants the counter runs
+of bench.py were given (--variant2d, --stage-variant, --variant3d), e.g. f64:6,f32:3,mixed:3.
 
 Counters are KiB per dispatch.  Each is scaled by what it reads for the plain copy kernel of
 known size that bench.py runs (torch copy_ of a 1 GiB float64 tensor: 1 GiB read and 1 GiB
@@ -25,17 +26,24 @@ GIB = float(1 << 30)
 
 # source files each kernel is compiled from (its .hip and every header it includes)
 SOURCES = {"stage2d": ["stage2d.hip", "tile2d.h", "point.h", "common.h", "kernels.h"],
-           "step2d": ["step2d.hip", "wave2d.h", "dpp.h", "point.h", "common.h", "kernels.h"]}
+           "step2d": ["step2d.hip", "wave2d.h", "dpp.h", "point.h", "common.h", "kernels.h"],
+           "pair3d": ["step3d.hip", "point.h", "common.h", "kernels.h"]}
 KEYS = {"stage2d": {"f64": ["stage2d_kernel<double, double, double"], "f32": ["stage2d_kernel<float, float, float"],
                     "mixed": ["stage2d_kernel<double, float, double", "stage2d_kernel<float, float, double"]},
         "step2d": {"f64": ["step2d_kernel<double, double"], "f32": ["step2d_kernel<float, float"],
-                   "mixed": ["step2d_kernel<float, double"]}}
+                   "mixed": ["step2d_kernel<float, double"]},
+        "pair3d": {"f64": ["pair3d_kernel<double, double, double"], "f32": ["pair3d_kernel<float, float, float"],
+                   "mixed": ["pair3d_kernel<double, float, double", "pair3d_kernel<float, float, double"]}}
 NAMES = {"stage2d": "nlse::stage2d_kernel (mean over the four RK4-stage launches)",
-         "step2d": "nlse::step2d_kernel (one launch per RK4 step)"}
+         "step2d": "nlse::step2d_kernel (one launch per RK4 step)",
+         "pair3d": "nlse::pair3d_kernel (mean over the two launches of an RK4 step)"}
+WORKLOADS = {"stage2d": ("gp2d_2048", "2D GP, 2049^2 nodes, bench.py defaults"),
+             "step2d": ("gp2d_2048", "2D GP, 2049^2 nodes, bench.py defaults"),
+             "pair3d": ("gp3d_512", "3D GP, 513^3 nodes, bench.py defaults")}
 
 
 def traffic_file(kind):
-    return os.path.join(ROOT, "profiles", f"traffic_{kind}_gp2d_2048.json")
+    return os.path.join(ROOT, "profiles", f"traffic_{kind}_{WORKLOADS[kind][0]}.json")
 
 
 def source_sha(kind):
@@ -54,7 +62,7 @@ def per_kernel(path, cname):
 
 
 def main(kind, variant2d, stage_variant, fetch_csv, write_csv):
-    variants = variant2d if kind == "step2d" else stage_variant
+    variants = stage_variant if kind == "stage2d" else variant2d
     var = {k: int(v) for k, v in (item.split(":") for item in variants.split(","))}
     F, W = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
     big = lambda vals: [v for v in vals if v > 0.25 * GIB]
@@ -69,15 +77,21 @@ def main(kind, variant2d, stage_variant, fetch_csv, write_csv):
         raw[prec] = {"fetch_bytes": sum(fv) / len(fv), "write_bytes": sum(wv) / len(wv), "launches": len(fv)}
         res[prec] = {"bytes": fF * raw[prec]["fetch_bytes"] + fW * raw[prec]["write_bytes"],
                      "variant": var.get(prec)}
-    out = {"kernel": NAMES[kind], "workload": "2D GP, 2049^2 nodes, bench.py defaults",
+    if kind == "pair3d":
+        args = (f"--precs f32 --steps 5 --warmup 1 --no-cpu-baseline --batch-steps 0 --no-learned --no-stencils "
+                f"--no-msd --no-stage3d --steps3d 3 --variant3d {variant2d}")
+        d = "prof3d"
+    else:
+        args = (f"--steps 5 --warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned "
+                f"--variant2d {variant2d} --stage-variant {stage_variant}")
+        d = "prof"
+    out = {"kernel": NAMES[kind], "workload": WORKLOADS[kind][1],
            "source_sha": source_sha(kind), "sources": SOURCES[kind],
            "per_launch_bytes": res, "raw_counter_bytes": raw,
            "scale_factors": {"FETCH_SIZE": fF, "WRITE_SIZE": fW,
                              "calibration": "torch copy_ of a 1 GiB float64 tensor: 1 GiB read, 1 GiB written"},
-           "commands": [
-               f"cd /tmp && rocprofv3 --pmc {c} -d $R/gpurun_out/prof_{c} -o pmc --output-format csv "
-               f"-- python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned "
-               f"--variant2d {variant2d} --stage-variant {stage_variant}" for c in ("FETCH_SIZE", "WRITE_SIZE")]}
+           "commands": [f"cd /tmp && rocprofv3 --pmc {c} -d $R/gpurun_out/{d}_{c} -o pmc --output-format csv "
+                        f"-- python3 $R/bench.py {args}" for c in ("FETCH_SIZE", "WRITE_SIZE")]}
     json.dump(out, open(traffic_file(kind), "w"), indent=1)
     print(json.dumps(out, indent=1))
 
