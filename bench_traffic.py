@@ -1,7 +1,7 @@
 """Turn two rocprofv3 counter runs of bench.py into per-launch HBM traffic of a 2D kernel.
 
 Usage: python bench_traffic.py <step2d|stage2d> <variant2d> <stage_variant> <fetch_collection.csv> <write_collection.csv>
-       python bench_traffic.py pair3d <variant3d> - <fetch_collection.csv> <write_collection.csv>
+       python bench_traffic.py pair3d <variant3d> - <fetch_collection.csv> <write_collection.csv> [<calibration.json>]
        python bench_traffic.py valu <variant2d> <valu_counter_collection.csv>   (VALU issue of the whole-step kernel)
 
 <variant2d>, <stage_variant> and <variant3d> are the per-precision kernel variants the counter runs
@@ -9,7 +9,9 @@ of bench.py were given (--variant2d, --stage-variant, --variant3d), e.g. f64:6,f
 
 Counters are KiB per dispatch.  Each is scaled by what it reads for the plain copy kernel of
 known size that bench.py runs (torch copy_ of a 1 GiB float64 tensor: 1 GiB read and 1 GiB
-written), then averaged over all launches of the kernel for each precision.  The result goes
+written), then averaged over all launches of the kernel for each precision.  A run whose own
+large copies include other transfers (the 3D run uploads 1-2 GB fields) takes the factors from
+the JSON of a 2D counter run of the same session instead (optional last argument).  The result goes
 to profiles/traffic_<kind>_gp2d_2048.json together with a hash of the kernel's sources;
 bench.py reports it only while the sources still match.
 """
@@ -61,13 +63,19 @@ def per_kernel(path, cname):
     return d
 
 
-def main(kind, variant2d, stage_variant, fetch_csv, write_csv):
+def main(kind, variant2d, stage_variant, fetch_csv, write_csv, calib_json=None):
     variants = stage_variant if kind == "stage2d" else variant2d
     var = {k: int(v) for k, v in (item.split(":") for item in variants.split(","))}
     F, W = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
-    big = lambda vals: [v for v in vals if v > 0.25 * GIB]
-    cf, cw = big(F["__amd_rocclr_copyBuffer"]), big(W["__amd_rocclr_copyBuffer"])
-    fF, fW = GIB / (sum(cf) / len(cf)), GIB / (sum(cw) / len(cw))
+    if calib_json:
+        sf = json.load(open(calib_json))["scale_factors"]
+        fF, fW = sf["FETCH_SIZE"], sf["WRITE_SIZE"]
+        calib = f"factors of {os.path.basename(calib_json)} (same session): " + sf["calibration"]
+    else:
+        big = lambda vals: [v for v in vals if v > 0.25 * GIB]
+        cf, cw = big(F["__amd_rocclr_copyBuffer"]), big(W["__amd_rocclr_copyBuffer"])
+        fF, fW = GIB / (sum(cf) / len(cf)), GIB / (sum(cw) / len(cw))
+        calib = "torch copy_ of a 1 GiB float64 tensor: 1 GiB read, 1 GiB written"
     res, raw = {}, {}
     for prec, keys in KEYS[kind].items():
         fv = [v for k in F for key in keys if key in k for v in F[k]]
@@ -88,8 +96,7 @@ def main(kind, variant2d, stage_variant, fetch_csv, write_csv):
     out = {"kernel": NAMES[kind], "workload": WORKLOADS[kind][1],
            "source_sha": source_sha(kind), "sources": SOURCES[kind],
            "per_launch_bytes": res, "raw_counter_bytes": raw,
-           "scale_factors": {"FETCH_SIZE": fF, "WRITE_SIZE": fW,
-                             "calibration": "torch copy_ of a 1 GiB float64 tensor: 1 GiB read, 1 GiB written"},
+           "scale_factors": {"FETCH_SIZE": fF, "WRITE_SIZE": fW, "calibration": calib},
            "commands": [f"cd /tmp && rocprofv3 --pmc {c} -d $R/gpurun_out/{d}_{c} -o pmc --output-format csv "
                         f"-- python3 $R/bench.py {args}" for c in ("FETCH_SIZE", "WRITE_SIZE")]}
     json.dump(out, open(traffic_file(kind), "w"), indent=1)
@@ -133,4 +140,4 @@ if __name__ == "__main__":
     if sys.argv[1] == "valu":
         valu(sys.argv[2], sys.argv[3])
     else:
-        main(*sys.argv[1:6])
+        main(*sys.argv[1:7])
