@@ -174,7 +174,7 @@ int nlse_get_stencil(const nlse_ctx *c);
 
 /* Autotuner: times `reps` RK4 steps of every variant on this context's own arrays
  * (twice, keeping the fastest), selects the fastest and caches the choice for the
- * process under (ndim, precision, n, stencil).  Later calls reuse the cached choice unless
+ * process under (ndim, precision, n, stencil, boundary rule).  Later calls reuse the cached choice unless
  * force != 0.  Needs a field (nlse_set_field).  The field is saved to a temporary
  * device buffer first and restored afterwards, so the integration state is unchanged;
  * NLSE_E_NOMEM if that buffer cannot be allocated.  Waits for the stream.  The chosen

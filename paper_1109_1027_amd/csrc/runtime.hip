@@ -78,13 +78,13 @@ static void free_ctx(nlse_ctx *c)
 }
 
 // Autotuner results shared by every context of the same shape in the process.
-using TuneKey = std::tuple<int, int, int64_t, int64_t, int64_t, int>;   // dim, precision, nx, ny, nz, stencil
+using TuneKey = std::tuple<int, int, int64_t, int64_t, int64_t, int, int>;   // dim, precision, n, stencil, bc
 static std::map<TuneKey, int> g_tuned;
 static std::mutex g_tuned_mu;
 
 static TuneKey tune_key(const nlse_ctx *c)
 {
-    return TuneKey(c->p.ndim, (int)c->prec, c->L.nx, c->L.ny, c->L.nz, c->stencil);
+    return TuneKey(c->p.ndim, (int)c->prec, c->L.nx, c->L.ny, c->L.nz, c->stencil, (int)c->p.bc);
 }
 
 static hipError_t launch_stage(nlse_ctx *c, int stage, double dt, int variant)
@@ -248,7 +248,7 @@ int nlse_autotune(nlse_ctx *c, int reps, int force, int *chosen)
         {
             std::lock_guard<std::mutex> g(g_tuned_mu);
             auto it = g_tuned.find(tune_key(c));
-            if (!force && it != g_tuned.end()) {
+            if (!force && it != g_tuned.end() && it->second < nv) {
                 c->variant = it->second;
                 if (chosen) *chosen = c->variant;
                 return NLSE_OK;

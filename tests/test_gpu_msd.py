@@ -153,3 +153,18 @@ def test_msd_2d_batch_rejected(gpu):
     with pytest.raises(gpu.NLSEError) as e:
         gpu.Batch([spec], prec="f32")
     assert e.value.code == -6
+
+
+def test_msd_autotune_not_shared_with_dirichlet(gpu):
+    """A Dirichlet context of the same shape tunes to a whole-step variant that MSD does not
+    have; the MSD context must tune on its own and keep its boundary rule."""
+    g, psi = vortex_case(96)
+    d = gpu.Solver(2, g.n, g.h, 0.5, -1.0, None, "dirichlet", "f32")
+    d.set_field(psi.astype(np.complex64))
+    d.autotune(reps=2, force=True)
+    d.close()
+    m = gpu.Solver(2, g.n, g.h, 0.5, -1.0, None, "msd", "f32")
+    m.set_field(psi.astype(np.complex64))
+    v = m.autotune(reps=2)
+    assert 0 <= v < m.variant_count() and m.launches_per_step() == 12
+    m.close()
