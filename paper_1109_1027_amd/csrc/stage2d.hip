@@ -11,10 +11,12 @@
 //
 // Boundary closure.  The per-axis form needs D^a on the face nodes normal to a.
 // They are D^a_b = Lap_b - (tangential second difference), where Lap_b is the
-// Dirichlet step-1 value of Eq. dbc_lap.  With these face values the per-axis
-// and single-storage forms (Eq. 2d2shocs1-2) are algebraically identical.  Under
-// Dirichlet the boundary values never change, so D^a_b are constants computed
-// once per field (launch_boundary_d) and read here only by boundary tiles.
+// step-1 boundary value (Eq. dbc_lap, or Eq. msdbc_lap under MSD).  With these
+// face values the per-axis and single-storage forms (Eq. 2d2shocs1-2) are
+// algebraically identical.  Under Dirichlet the boundary values never change, so
+// D^a_b are constants computed once per field (launch_boundary_d); under MSD
+// msd.hip forms them from the stage's input before each launch and updates the
+// boundary nodes after it.  Either way only boundary tiles read them.
 //
 // Tiling.  A wave owns 64 consecutive interior columns (aligned, one row segment
 // = one coalesced access) and RW rows (RW = 4, 8 or 16: the tile variants the

@@ -22,9 +22,10 @@
 // march, the z tests are block-uniform, and the RK4 stage is a template
 // parameter so each stage loads only what it uses.
 //
-// Face closure values D^a_b (boundary-face nodes) are the Dirichlet constants of
-// launch_boundary_d; see stage2d.hip for why the per-axis and single-storage
-// forms then coincide.
+// Face closure values D^a_b (boundary-face nodes) come from the face arrays: the
+// Dirichlet constants of launch_boundary_d, or under MSD the values msd.hip forms
+// from the stage's input before each launch; see stage2d.hip for why the per-axis
+// and single-storage forms then coincide.
 #include "kernels.h"
 #include "point.h"
 
