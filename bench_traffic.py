@@ -20,6 +20,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -48,10 +49,17 @@ def traffic_file(kind):
     return os.path.join(ROOT, "profiles", f"traffic_{kind}_{WORKLOADS[kind][0]}.json")
 
 
-def source_sha(kind):
+def _code_only(text):
+    """Source text without comments and blank space: a comment edit does not change the kernel."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(" ".join(line.split()) for line in text.splitlines() if line.strip())
+
+
+def source_sha(kind, root=CSRC):
     h = hashlib.sha256()
     for f in SOURCES[kind]:
-        h.update(open(os.path.join(CSRC, f), "rb").read())
+        h.update(_code_only(open(os.path.join(root, f), encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 
