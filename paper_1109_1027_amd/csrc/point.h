@@ -21,6 +21,16 @@ __device__ __forceinline__ C<R> d2(C<R> lo, C<R> c, C<R> hi, R ih2)
     return mk<R>((fmar(R(-2), c.x, hi.x) + lo.x) * ih2, (fmar(R(-2), c.y, hi.y) + lo.y) * ih2);
 }
 
+// Step 1 along one axis without the 1/h^2 factor, (Psi_{+1} - 2 Psi_0) + Psi_{-1}: the 2D
+// kernels move 1/h^2 (and a) into the step-2 coefficients (lap2a), two multiplications
+// fewer per difference.
+template <typename R>
+__device__ __forceinline__ C<R> d2u(C<R> lo, C<R> c, C<R> hi)
+{
+#pragma clang fp contract(off)
+    return mk<R>(fmar(R(-2), c.x, hi.x) + lo.x, fmar(R(-2), c.y, hi.y) + lo.y);
+}
+
 // Step 2 of the per-axis 2D form (Sec. 2.2, Eqs. 2d2shocMs1-2): sum over both axes of
 // D^a - (1/12) delta_a^2 D^a, written as (7/6)(D^x + D^y) - (1/12)(neighbour sums).
 template <typename R>
@@ -43,6 +53,14 @@ __device__ __forceinline__ C<R> lap3(C<R> dx, C<R> dy, C<R> dz, C<R> dxl, C<R> d
     const R bx = ((dxr.x + dxl.x) + (dyu.x + dyd.x)) + (dzp.x + dzm.x);
     const R by = ((dxr.y + dxl.y) + (dyu.y + dyd.y)) + (dzp.y + dzm.y);
     return mk<R>(fmar(c76, ax, -(c112 * bx)), fmar(c76, ay, -(c112 * by)));
+}
+
+// a Lap of the per-axis 2D form from unscaled second differences (d2u):
+// A76 = a (7/6) / h^2, A112 = a (1/12) / h^2; otherwise as lap2.
+template <typename R>
+__device__ __forceinline__ C<R> lap2a(C<R> dx, C<R> dy, C<R> dxl, C<R> dxr, C<R> dyd, C<R> dyu, R A76, R A112)
+{
+    return lap2<R>(dx, dy, dxl, dxr, dyd, dyu, A76, A112);
 }
 
 // Non-compact fourth-order second difference along one axis (Sec. 2.1, the stencil the
@@ -103,6 +121,32 @@ __device__ __forceinline__ C<M> dirichlet_lapb(C<M> u, M v, M s, M ia)
 #pragma clang fp contract(off)
     const M f = -(nonlin<M>(u, v, s) * ia);
     return mk<M>(f * u.x, f * u.y);
+}
+
+// F from a Lap (lap2a): F = i [a Lap + (s |Psi|^2 - V) Psi].
+template <typename R>
+__device__ __forceinline__ C<R> rhs_a(C<R> alap, C<R> u, R v, R s)
+{
+#pragma clang fp contract(off)
+    const R nl = nonlin<R>(u, v, s);
+    return mk<R>(-fmar(nl, u.y, alap.y), fmar(nl, u.x, alap.x));
+}
+
+// The 2D kernels' step-2 coefficients and the factor h^2 that turns a face value D^a_b
+// (scaled like a second derivative) into the unscaled form of d2u.
+template <typename R>
+struct Lap2Coef {
+    R A76, A112, h2;
+};
+template <typename R>
+__host__ __device__ inline Lap2Coef<R> lap2_coef(double a, double c76, double c112, double ih2)
+{
+    return Lap2Coef<R>{(R)(a * c76 * ih2), (R)(a * c112 * ih2), (R)(1.0 / ih2)};
+}
+template <typename R>
+__device__ __forceinline__ C<R> unscaled(C<R> d, R h2)
+{
+    return mk<R>(d.x * h2, d.y * h2);
 }
 
 // K_tot accumulation of stages 2 and 3: K + 2F (2F is exact).

@@ -31,7 +31,8 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
     const int64_t x = x0 + lane;
     const bool xnode = valid && x <= L.nx;
 
-    const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
+    const R a = (R)A.c.a, s = (R)A.c.s;
+    const Lap2Coef<R> lc = lap2_coef<R>(A.c.a, A.c.c76, A.c.c112, A.c.ih2);
     const R ck = (R)A.c.ck;
     const int stage = A.stage;
     const C<IN> *in = (const C<IN> *)A.in;
@@ -85,20 +86,20 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
     C<R> dx[RW];
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
-        dx[r] = d2<R>(lds[wv][r][lane + 1], lds[wv][r][lane + 2], lds[wv][r][lane + 3], ih2);
-        if (xnode && x == L.nx && y0 + r <= L.ny) dx[r] = DBx[(L.ny + 1) + y0 + r];   // face x = nx
+        dx[r] = d2u<R>(lds[wv][r][lane + 1], lds[wv][r][lane + 2], lds[wv][r][lane + 3]);
+        if (xnode && x == L.nx && y0 + r <= L.ny) dx[r] = unscaled<R>(DBx[(L.ny + 1) + y0 + r], lc.h2);   // face x = nx
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r) ldx[wv][r][lane + 1] = dx[r];
     if (valid && lane < 2 * RW) {
         const int r = lane >> 1, side = lane & 1;
         const int c = side ? W + 2 : 1;               // LDS column of x0+64 or x0-1
-        C<R> hdx = d2<R>(lds[wv][r][c - 1], lds[wv][r][c], lds[wv][r][c + 1], ih2);
+        C<R> hdx = d2u<R>(lds[wv][r][c - 1], lds[wv][r][c], lds[wv][r][c + 1]);
         const int64_t hx = side ? x0 + W : x0 - 1;
         const int64_t y = y0 + r;
         if (y <= L.ny) {
-            if (hx == 0) hdx = DBx[y];
-            else if (hx == L.nx) hdx = DBx[(L.ny + 1) + y];
+            if (hx == 0) hdx = unscaled<R>(DBx[y], lc.h2);
+            else if (hx == L.nx) hdx = unscaled<R>(DBx[(L.ny + 1) + y], lc.h2);
         }
         ldx[wv][r][side ? W + 1 : 0] = hdx;
     }
@@ -108,9 +109,9 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
 #pragma unroll
     for (int j = 0; j < RW + 2; ++j) {
         const int64_t y = y0 - 1 + j;
-        dy[j] = d2<R>(col[j], col[j + 1], col[j + 2], ih2);
-        if (xnode && y == 0) dy[j] = DBy[x];
-        if (xnode && y == L.ny) dy[j] = DBy[(L.nx + 1) + x];
+        dy[j] = d2u<R>(col[j], col[j + 1], col[j + 2]);
+        if (xnode && y == 0) dy[j] = unscaled<R>(DBy[x], lc.h2);
+        if (xnode && y == L.ny) dy[j] = unscaled<R>(DBy[(L.nx + 1) + x], lc.h2);
     }
     __syncthreads();
 
@@ -119,11 +120,14 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
     for (int r = 0; r < RW; ++r) {
         const int64_t y = y0 + r;
         if (!(xnode && x < L.nx && y < L.ny)) continue;
-        C<R> lap;
+        const C<R> u = col[r + 2];
+        C<R> F;
         if constexpr (ST == 0) {
-            lap = lap2<R>(dx[r], dy[r + 1], ldx[wv][r][lane], ldx[wv][r][lane + 2], dy[r], dy[r + 2], c76, c112);
-        } else if constexpr (ST == 2) {
-            lap = cadd<R>(dx[r], dy[r + 1]);
+            const C<R> alap = lap2a<R>(dx[r], dy[r + 1], ldx[wv][r][lane], ldx[wv][r][lane + 2], dy[r], dy[r + 2],
+                                       lc.A76, lc.A112);
+            F = rhs_a<R>(alap, u, vv[r], s);
+        } else if constexpr (ST == 2) {   // a/h^2 (D^x + D^y) from the unscaled differences
+            F = rhs_a<R>(cscale<R>((R)(A.c.a * A.c.ih2), cadd<R>(dx[r], dy[r + 1])), u, vv[r], s);
         } else {
             const R i12h2 = (R)(A.c.ih2 / 12.0);
             const C<R> c = col[r + 2];
@@ -133,10 +137,9 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
             const C<R> ym1 = col[r + 1], yp1 = col[r + 3];
             const C<R> ym2 = y == 1 ? ghost<R>(ym1, c) : col[r];
             const C<R> yp2 = y == L.ny - 1 ? ghost<R>(yp1, c) : col[r + 4];
-            lap = cadd<R>(d4nc<R>(xm2, xm1, c, xp1, xp2, i12h2), d4nc<R>(ym2, ym1, c, yp1, yp2, i12h2));
+            const C<R> lap = cadd<R>(d4nc<R>(xm2, xm1, c, xp1, xp2, i12h2), d4nc<R>(ym2, ym1, c, yp1, yp2, i12h2));
+            F = rhs<R>(lap, u, vv[r], a, s);
         }
-        const C<R> u = col[r + 2];
-        const C<R> F = rhs<R>(lap, u, vv[r], a, s);
         const int64_t p = L.idx(x, y, 0);
         if (stage == 1) {
             const C<M> base = in_is_r ? cvt<M, R>(u) : pn[r];

@@ -43,7 +43,8 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
     const int y0 = 1 + SEG * seg, y1 = min(y0 + SEG, ny);
     const int jb = y0 - HALO;               // row of Psi^n that enters at t = 0
 
-    const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
+    const R s = (R)A.c.s;
+    const Lap2Coef<R> lc = lap2_coef<R>(A.c.a, A.c.c76, A.c.c112, A.c.ih2);
     R ck[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) ck[i] = (R)A.ck[i];
@@ -53,14 +54,14 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
     const C<R> *__restrict__ DBx = (const C<R> *)A.DB[0];
     const C<R> *__restrict__ DBy = (const C<R> *)A.DB[1];
 
-    sdy[0][lane] = xin ? DBy[x] : czero<R>();
-    sdy[1][lane] = xin ? DBy[nx + 1 + x] : czero<R>();
+    sdy[0][lane] = xin ? unscaled<R>(DBy[x], lc.h2) : czero<R>();   // unscaled, like d2u
+    sdy[1][lane] = xin ? unscaled<R>(DBy[nx + 1 + x], lc.h2) : czero<R>();
     if (has_face) {
         for (int i = lane; i < FR; i += 64) {
             const int r = jb - HALO + i;
             const bool ok = r >= 0 && r <= ny;
-            sdx[0][i] = ok ? DBx[r] : czero<R>();
-            sdx[1][i] = ok ? DBx[ny + 1 + r] : czero<R>();
+            sdx[0][i] = ok ? unscaled<R>(DBx[r], lc.h2) : czero<R>();
+            sdx[1][i] = ok ? unscaled<R>(DBx[ny + 1 + r], lc.h2) : czero<R>();
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -116,7 +117,7 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
             for (int st = 0; st < 4; ++st) {
                 const int m = j - 2 * st;   // newest input row of this stage
                 U[st][q0] = in;
-                C<R> dy = d2<R>(U[st][q1], U[st][q2], U[st][q0], ih2);   // D^y at row m-1
+                C<R> dy = d2u<R>(U[st][q1], U[st][q2], U[st][q0]);   // h^2 D^y at row m-1
                 if (m - 1 == 0) dy = sdy[0][lane];
                 if (m - 1 == ny) dy = sdy[1][lane];
                 D[st][q0] = dy;
@@ -125,13 +126,14 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                     const int r = m - 2;    // output row
                     const int kr = (p + 18 - 2 * (st + 1)) % 9;
                     const C<R> u = U[st][q1];
-                    C<R> dx = d2<R>(clane_prev<R>(u), u, clane_next<R>(u), ih2);
+                    C<R> dx = d2u<R>(clane_prev<R>(u), u, clane_next<R>(u));
                     if (has_face) {
                         const C<R> f = sdx[x == 0 ? 0 : 1][r - jb + HALO];
                         if (xface) dx = f;
                     }
-                    const C<R> lap = lap2<R>(dx, D[st][q2], clane_prev<R>(dx), clane_next<R>(dx), D[st][q1], D[st][q0], c76, c112);
-                    const C<R> F = rhs<R>(lap, u, Vq[kr], a, s);
+                    const C<R> alap = lap2a<R>(dx, D[st][q2], clane_prev<R>(dx), clane_next<R>(dx), D[st][q1], D[st][q0],
+                                               lc.A76, lc.A112);
+                    const C<R> F = rhs_a<R>(alap, u, Vq[kr], s);
                     const bool upd = xint && r >= 1 && r < ny;
                     if (st == 0) {
                         Kq[kr] = F;
