@@ -132,16 +132,16 @@ __device__ __forceinline__ C<R> rhs_a(C<R> alap, C<R> u, R v, R s)
     return mk<R>(-fmar(nl, u.y, alap.y), fmar(nl, u.x, alap.x));
 }
 
-// The 2D kernels' step-2 coefficients and the factor h^2 that turns a face value D^a_b
+// The step-2 coefficients of the 2D and 3D kernels and the factor h^2 that turns a face value D^a_b
 // (scaled like a second derivative) into the unscaled form of d2u.
 template <typename R>
-struct Lap2Coef {
+struct Step2Coef {
     R A76, A112, h2;
 };
 template <typename R>
-__host__ __device__ inline Lap2Coef<R> lap2_coef(double a, double c76, double c112, double ih2)
+__host__ __device__ inline Step2Coef<R> step2_coef(double a, double c76, double c112, double ih2)
 {
-    return Lap2Coef<R>{(R)(a * c76 * ih2), (R)(a * c112 * ih2), (R)(1.0 / ih2)};
+    return Step2Coef<R>{(R)(a * c76 * ih2), (R)(a * c112 * ih2), (R)(1.0 / ih2)};
 }
 template <typename R>
 __device__ __forceinline__ C<R> unscaled(C<R> d, R h2)

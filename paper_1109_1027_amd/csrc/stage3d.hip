@@ -56,7 +56,8 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
     const bool xface = col_ok && x == nx, yface = col_ok && y == ny;
     const int cidx = y * px + x + ox;                    // own column, plane 0
 
-    const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
+    const R s = (R)A.c.s;
+    const Step2Coef<R> lc = step2_coef<R>(A.c.a, A.c.c76, A.c.c112, A.c.ih2);   // 1/h^2 and a folded in
     const R ck = (R)A.c.ck;
     const C<IN> *in = (const C<IN> *)A.in;
     const C<R> *DBx = (const C<R> *)A.DB[0];
@@ -105,11 +106,11 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
     auto ldp = [&](int zz, int idx, bool ok) -> C<R> {   // Psi_in at plane zz (block-uniform bounds)
         return (ok && zz >= 0 && zz <= nz) ? cvt<R, IN>(in[zz * plane + idx]) : czero<R>();
     };
-    auto d2 = [&](const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> { return nlse::d2<R>(m, c, p, ih2); };
+    auto d2 = [&](const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> { return d2u<R>(m, c, p); };
     auto dz_at = [&](int zz, const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> {
         if (!col_ok) return czero<R>();
-        if (zz == 0) return DBz[y * (nx + 1) + x];
-        if (zz == nz) return DBz[fz + y * (nx + 1) + x];
+        if (zz == 0) return unscaled<R>(DBz[y * (nx + 1) + x], lc.h2);
+        if (zz == nz) return unscaled<R>(DBz[fz + y * (nx + 1) + x], lc.h2);
         return d2(m, c, p);
     };
     struct Ops { C<M> pn; C<R> kt; R vv; };
@@ -154,29 +155,29 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
         __syncthreads();
         C<R> dx = d2(sp[ty + 2][tx + 1], q[2], sp[ty + 2][tx + 3]);
         C<R> dy = d2(sp[ty + 1][tx + 2], q[2], sp[ty + 3][tx + 2]);
-        if (xface) dx = DBx[fx + z * (ny + 1) + y];
-        if (yface) dy = DBy[fy + z * (nx + 1) + x];
+        if (xface) dx = unscaled<R>(DBx[fx + z * (ny + 1) + y], lc.h2);
+        if (yface) dy = unscaled<R>(DBy[fy + z * (nx + 1) + x], lc.h2);
         sdx[ty][tx + 1] = dx;
         sdy[ty + 1][tx] = dy;
         if (hdx_role) {
             const int c = hdx_side ? W + 2 : 1;
             C<R> hdx = d2(sp[hdx_r + 2][c - 1], sp[hdx_r + 2][c], sp[hdx_r + 2][c + 1]);
-            if (hdx_face >= 0) hdx = DBx[hdx_face * fx + z * (ny + 1) + hdx_row];
+            if (hdx_face >= 0) hdx = unscaled<R>(DBx[hdx_face * fx + z * (ny + 1) + hdx_row], lc.h2);
             sdx[hdx_r][hdx_side ? W + 1 : 0] = hdx;
         }
         if (hdy_role) {
             const int r = hdy_side ? TYB + 2 : 1;
             C<R> hdy = d2(sp[r - 1][hdy_c + 2], sp[r][hdy_c + 2], sp[r + 1][hdy_c + 2]);
-            if (hdy_face >= 0) hdy = DBy[hdy_face * fy + z * (nx + 1) + hdy_col];
+            if (hdy_face >= 0) hdy = unscaled<R>(DBy[hdy_face * fy + z * (nx + 1) + hdy_col], lc.h2);
             sdy[hdy_side ? TYB + 1 : 0][hdy_c] = hdy;
         }
         __syncthreads();
         if (upd_col) {
             const int p = z * plane + cidx;
-            const C<R> lap = lap3<R>(dx, dy, dz0, sdx[ty][tx], sdx[ty][tx + 2], sdy[ty][tx], sdy[ty + 2][tx], dzm, dzp,
-                                     c76, c112);
+            const C<R> alap = lap3<R>(dx, dy, dz0, sdx[ty][tx], sdx[ty][tx + 2], sdy[ty][tx], sdy[ty + 2][tx], dzm,
+                                      dzp, lc.A76, lc.A112);
             const C<R> u = q[2];
-            const C<R> F = rhs<R>(lap, u, ops.vv, a, s);
+            const C<R> F = rhs_a<R>(alap, u, ops.vv, s);
             if (STAGE == 1) {
                 const C<M> base = in_is_r ? cvt<M, R>(u) : ops.pn;
                 K[p] = F;

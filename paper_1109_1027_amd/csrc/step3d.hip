@@ -65,7 +65,8 @@ __global__ __launch_bounds__(PW * TY) void pair3d_kernel(Step3DArgs A, int tiles
     const bool col_out = col_int && tx >= 2 && tx < PW - 2 && ty >= 2 && ty < TY - 2;
     const int cidx = col_in ? y * px + x + ox : 0;          // own column, plane 0
 
-    const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
+    const R s = (R)A.c.s;
+    const Step2Coef<R> lc = step2_coef<R>(A.c.a, A.c.c76, A.c.c112, A.c.ih2);   // 1/h^2 and a folded in
     const R ck_a = (R)A.ck[PAIR == 1 ? 0 : 2], ck_b = (R)A.ck[PAIR == 1 ? 1 : 3];
     const C<IN> *in = PAIR == 1 ? (const C<IN> *)A.psin : (const C<IN> *)A.B;
     const C<M> *psin = (const C<M> *)A.psin;
@@ -120,9 +121,9 @@ __global__ __launch_bounds__(PW * TY) void pair3d_kernel(Step3DArgs A, int tiles
     // D^z from three planes of a column, or the z-face value on a boundary plane
     auto dz_at = [&](int zz, const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> {
         if (!col_in || zz < 0 || zz > nz) return czero<R>();
-        if (zz == 0) return DBz[y * (nx + 1) + x];
-        if (zz == nz) return DBz[fz + y * (nx + 1) + x];
-        return d2<R>(m, c, p, ih2);
+        if (zz == 0) return unscaled<R>(DBz[y * (nx + 1) + x], lc.h2);
+        if (zz == nz) return unscaled<R>(DBz[fz + y * (nx + 1) + x], lc.h2);
+        return d2u<R>(m, c, p);
     };
     struct Ops { C<M> pn; C<R> kt; R vv; };   // alpha's update operands at one plane
     auto ld_ops = [&](int zz) -> Ops {
@@ -185,45 +186,45 @@ __global__ __launch_bounds__(PW * TY) void pair3d_kernel(Step3DArgs A, int tiles
             const C<R>(*pa)[PW] = sa[(zb + 3) % 3];
             const int xl = max(tx - 1, 0), xr = min(tx + 1, PW - 1), yl = max(ty - 1, 0), yr = min(ty + 1, TY - 1);
             const C<R> ub = pa[ty][tx];
-            bdx = d2<R>(pa[ty][xl], ub, pa[ty][xr], ih2);   // tile-border threads: unused
-            bdy = d2<R>(pa[yl][tx], ub, pa[yr][tx], ih2);
+            bdx = d2u<R>(pa[ty][xl], ub, pa[ty][xr]);   // tile-border threads: unused
+            bdy = d2u<R>(pa[yl][tx], ub, pa[yr][tx]);
             if (col_in) {   // zb lies in 1 .. nz-1
-                if (x == 0) bdx = DBx[zb * (ny + 1) + y];
-                else if (x == nx) bdx = DBx[fx + zb * (ny + 1) + y];
-                if (y == 0) bdy = DBy[zb * (nx + 1) + x];
-                else if (y == ny) bdy = DBy[fy + zb * (nx + 1) + x];
+                if (x == 0) bdx = unscaled<R>(DBx[zb * (ny + 1) + y], lc.h2);
+                else if (x == nx) bdx = unscaled<R>(DBx[fx + zb * (ny + 1) + y], lc.h2);
+                if (y == 0) bdy = unscaled<R>(DBy[zb * (nx + 1) + x], lc.h2);
+                else if (y == ny) bdy = unscaled<R>(DBy[fy + zb * (nx + 1) + x], lc.h2);
             }
             sbx[ty][tx] = bdx;
             sby[ty][tx] = bdy;
         }
-        C<R> dx = d2<R>(sp[ty + 2][tx + 1], u, sp[ty + 2][tx + 3], ih2);
-        C<R> dy = d2<R>(sp[ty + 1][tx + 2], u, sp[ty + 3][tx + 2], ih2);
+        C<R> dx = d2u<R>(sp[ty + 2][tx + 1], u, sp[ty + 2][tx + 3]);
+        C<R> dy = d2u<R>(sp[ty + 1][tx + 2], u, sp[ty + 3][tx + 2]);
         if (col_in && zin) {
-            if (x == 0) dx = DBx[za * (ny + 1) + y];
-            else if (x == nx) dx = DBx[fx + za * (ny + 1) + y];
-            if (y == 0) dy = DBy[za * (nx + 1) + x];
-            else if (y == ny) dy = DBy[fy + za * (nx + 1) + x];
+            if (x == 0) dx = unscaled<R>(DBx[za * (ny + 1) + y], lc.h2);
+            else if (x == nx) dx = unscaled<R>(DBx[fx + za * (ny + 1) + y], lc.h2);
+            if (y == 0) dy = unscaled<R>(DBy[za * (nx + 1) + x], lc.h2);
+            else if (y == ny) dy = unscaled<R>(DBy[fy + za * (nx + 1) + x], lc.h2);
         }
         sdx[ty][tx + 1] = dx;
         sdy[ty + 1][tx] = dy;
         if (hdx_role) {
             const int c = hdx_side ? PW + 2 : 1;
-            C<R> hdx = d2<R>(sp[hdx_r + 2][c - 1], sp[hdx_r + 2][c], sp[hdx_r + 2][c + 1], ih2);
-            if (hdx_face >= 0 && zin) hdx = DBx[hdx_face * fx + za * (ny + 1) + hdx_row];
+            C<R> hdx = d2u<R>(sp[hdx_r + 2][c - 1], sp[hdx_r + 2][c], sp[hdx_r + 2][c + 1]);
+            if (hdx_face >= 0 && zin) hdx = unscaled<R>(DBx[hdx_face * fx + za * (ny + 1) + hdx_row], lc.h2);
             sdx[hdx_r][hdx_side ? PW + 1 : 0] = hdx;
         }
         if (hdy_role) {
             const int r = hdy_side ? TY + 2 : 1;
-            C<R> hdy = d2<R>(sp[r - 1][hdy_c + 2], sp[r][hdy_c + 2], sp[r + 1][hdy_c + 2], ih2);
-            if (hdy_face >= 0 && zin) hdy = DBy[hdy_face * fy + za * (nx + 1) + hdy_col];
+            C<R> hdy = d2u<R>(sp[r - 1][hdy_c + 2], sp[r][hdy_c + 2], sp[r + 1][hdy_c + 2]);
+            if (hdy_face >= 0 && zin) hdy = unscaled<R>(DBy[hdy_face * fy + za * (nx + 1) + hdy_col], lc.h2);
             sdy[hdy_side ? TY + 1 : 0][hdy_c] = hdy;
         }
         __syncthreads();
         C<R> ua = u, ka = czero<R>();   // alpha's field (boundary: unchanged) and K after alpha
         if (col_int && za >= 1 && za < nz) {
-            const C<R> lap = lap3<R>(dx, dy, dza[1], sdx[ty][tx], sdx[ty][tx + 2], sdy[ty][tx], sdy[ty + 2][tx],
-                                     dza[0], dza[2], c76, c112);
-            const C<R> F = rhs<R>(lap, u, ops.vv, a, s);
+            const C<R> alap = lap3<R>(dx, dy, dza[1], sdx[ty][tx], sdx[ty][tx + 2], sdy[ty][tx], sdy[ty + 2][tx],
+                                      dza[0], dza[2], lc.A76, lc.A112);
+            const C<R> F = rhs_a<R>(alap, u, ops.vv, s);
             if (PAIR == 1) {   // stage 1: K = F, field Psi^n + (k/2) F
                 ka = F;
                 ua = cvt<R, M>(axpy_m<R, M>(cvt<M, IN>(qi[2]), ck_a, F));
@@ -255,9 +256,9 @@ __global__ __launch_bounds__(PW * TY) void pair3d_kernel(Step3DArgs A, int tiles
         if (beta) {
             const C<R> ub = qa[2];
             if (col_out) {
-                const C<R> lap = lap3<R>(bdx, bdy, dzb[1], sbx[ty][tx - 1], sbx[ty][tx + 1], sby[ty - 1][tx],
-                                         sby[ty + 1][tx], dzb[0], dzb[2], c76, c112);
-                const C<R> F = rhs<R>(lap, ub, vq[2], a, s);
+                const C<R> alap = lap3<R>(bdx, bdy, dzb[1], sbx[ty][tx - 1], sbx[ty][tx + 1], sby[ty - 1][tx],
+                                          sby[ty + 1][tx], dzb[0], dzb[2], lc.A76, lc.A112);
+                const C<R> F = rhs_a<R>(alap, ub, vq[2], s);
                 const int p = zb * plane + cidx;
                 if (PAIR == 1) {   // stage 2: K += 2F, B = Psi^n + (k/2) F (Psi^n at zb is qi[0])
                     Kout[p] = kacc<R>(kq[2], F);

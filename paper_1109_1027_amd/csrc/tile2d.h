@@ -32,7 +32,7 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
     const bool xnode = valid && x <= L.nx;
 
     const R a = (R)A.c.a, s = (R)A.c.s;
-    const Lap2Coef<R> lc = lap2_coef<R>(A.c.a, A.c.c76, A.c.c112, A.c.ih2);
+    const Step2Coef<R> lc = step2_coef<R>(A.c.a, A.c.c76, A.c.c112, A.c.ih2);
     const R ck = (R)A.c.ck;
     const int stage = A.stage;
     const C<IN> *in = (const C<IN> *)A.in;

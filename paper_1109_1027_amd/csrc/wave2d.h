@@ -44,7 +44,7 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
     const int jb = y0 - HALO;               // row of Psi^n that enters at t = 0
 
     const R s = (R)A.c.s;
-    const Lap2Coef<R> lc = lap2_coef<R>(A.c.a, A.c.c76, A.c.c112, A.c.ih2);
+    const Step2Coef<R> lc = step2_coef<R>(A.c.a, A.c.c76, A.c.c112, A.c.ih2);
     R ck[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) ck[i] = (R)A.ck[i];
