@@ -168,3 +168,22 @@ def test_msd_autotune_not_shared_with_dirichlet(gpu):
     v = m.autotune(reps=2)
     assert 0 <= v < m.variant_count() and m.launches_per_step() == 12
     m.close()
+
+
+@pytest.mark.parametrize("dim,prec", [(2, "f64"), (2, "mixed"), (3, "f32")])
+def test_msd_with_potential(gpu, orc, dim, prec):
+    """MSD with V != 0: the N_{b-1} - N_b term of Eq. msdbc_lap and the V in F_{b-1} both enter."""
+    g, psi = vortex_case(120) if dim == 2 else ring_case(32)
+    c = g.coords()
+    V = 0.02 * (c[0] + 0.5) ** 2 + 0.01 * c[1] + (0.005 * c[2] ** 2 if dim == 3 else 0.0)
+    P = orc.Problem(dim, g.n, g.h, 0.5, -1.0, V=V, bc="msd")
+    dt = 0.5 * P.max_dt(psi)
+    nst = 30 if dim == 2 else 8
+    say(f"[case] msd {dim}d with V, {prec}, {nst} steps")
+    sol = gpu.Solver(dim, g.n, g.h, 0.5, -1.0, V, "msd", prec)
+    sol.set_field(psi.astype(sol.dtype))
+    assert sol.max_dt() == pytest.approx(P.max_dt(psi), rel=1e-4 if prec != "f64" else 1e-12)
+    sol.step(nst, dt)
+    out = sol.get_field()
+    sol.close()
+    assert rel(out, P.rk4(psi, nst, dt)) <= TOL[prec]

@@ -132,7 +132,7 @@ def test_1d_soliton_full_run(gpu, orc, prec):
         assert err == pytest.approx(1.31e-4, rel=0.02)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
 def test_1d_msd_dark_soliton(gpu, orc, prec):
     sp = I.paper_fig1(0.25)
     g, ref, s, P = run_both(gpu, orc, sp, prec, 2000, dt=0.0005)

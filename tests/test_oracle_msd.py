@@ -147,3 +147,19 @@ def test_msd_per_axis_equals_single_storage(orc, dim):
     a = P.laplacian(psi)
     b = P.with_lap("axis").laplacian(psi)
     assert np.max(np.abs(a - b)) < 1e-11 * np.max(np.abs(a))
+
+
+def test_msd_symmetry_with_potential(orc):
+    """The same reflection symmetry with a potential even in x: V enters N at b and b-1."""
+    n = (9, 7)
+    x = 0.3 * np.arange(10) - 1.35
+    y = 0.3 * np.arange(8)
+    V = 0.4 * x[None, :] ** 2 + 0.2 * y[:, None]
+    P = orc.Problem(2, n, 0.3, 0.7, -1.3, V=V, bc="msd")
+    psi = _rough((8, 10), 7)
+    out = P.rk4(psi, 6, 0.004)
+    f = P.rk4(np.flip(psi, 1), 6, 0.004)
+    assert np.max(np.abs(f - np.flip(out, 1))) < 1e-13
+    # and V matters: the run differs from the one without it
+    Q = orc.Problem(2, n, 0.3, 0.7, -1.3, bc="msd")
+    assert np.max(np.abs(Q.rk4(psi, 6, 0.004) - out)) > 1e-4
