@@ -71,7 +71,7 @@ def run(gpu, n, h, psi, V, prec, variant, steps, dt):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
-@pytest.mark.parametrize("n", [(70, 70, 70), (61, 23, 9), (5, 4, 6), (130, 17, 40)])
+@pytest.mark.parametrize("n", [(70, 70, 70), (61, 23, 9), (5, 4, 6), (130, 17, 40), (2, 2, 2), (3, 2, 5)])
 def test_pairs_bitwise_equal_to_stage_kernels(gpu, prec, n):
     psi, V = smooth_field(n, 3, boundary_amp=0.3)
     h = 1.0 / max(n)
