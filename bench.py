@@ -174,11 +174,56 @@ def cpu_baseline(spec, budget_s=12.0, budget_1core_s=6.0):
         steps1, el1 = run(budget_1core_s, 10)
     finally:
         oracle.set_threads(cores)
+    # the 1D soliton (config 1) is small enough to run whole: its wall time beside the GPU's
+    import nlse_inputs as I
+    sp1 = I.config_soliton_1d(1024)
+    P1 = oracle.Problem.from_spec(sp1)
+    n1, dt1 = oracle.steps_for(sp1.t_end, P1.max_dt(sp1.psi0))
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        P1.rk4(sp1.psi0, n1, dt1)
+        el_1d = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
     return {"value": spec.interior_points * steps / el / 1e9, "unit": "Gpt·steps/s",
             "cores": cores, "kind": "oracle",
             "sample": f"{steps} RK4 steps of the FP64 oracle on the full {spec.grid.n + 1}^2 grid ({el:.1f} s, {cores} threads); "
                       f"{steps1} steps on 1 thread ({el1:.1f} s)",
-            "single_core_value": spec.interior_points * steps1 / el1 / 1e9}
+            "single_core_value": spec.interior_points * steps1 / el1 / 1e9,
+            "soliton1d_full_run_s_1thread": el_1d, "soliton1d_steps": n1}
+
+
+def bench_1d(P, I):
+    """Config 1 (1D bright soliton, 1025 nodes, to t = 10): one launch of the on-chip solver for
+    the whole run; wall time and the distance to the exact solution."""
+    import torch
+    sp = I.config_soliton_1d(1024)
+    (x,) = sp.grid.coords()
+    exact = I.bright_soliton(x, sp.t_end, 1.0, 1.0, 1.0, 0.5)
+    res = {"workload": "1D bright soliton, 1025 nodes, a = s = 1, t = 10, dt = 0.5 k_max (config 1)"}
+    for prec in ("f64", "f32"):
+        s = P.Solver.from_spec(sp, prec=prec)
+        s.set_field(sp.psi0)
+        nsteps = int(math.ceil(sp.t_end / (0.5 * s.max_dt())))
+        dt = sp.t_end / nsteps
+        s.step(10, dt)   # warm-up (discarded)
+        s.set_field(sp.psi0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(torch.cuda.current_stream())
+        s.step(nsteps, dt)
+        e1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        g = np.asarray(s.get_field(), np.complex128)
+        s.close()
+        err = float(np.linalg.norm(g - exact) / np.linalg.norm(exact))
+        res[prec] = {"steps": nsteps, "run_ms": ms, "us_per_step": 1e3 * ms / nsteps, "rel_l2_vs_exact": err,
+                     "launches": 1}
+        print(f"[bench] 1D soliton {prec}: {nsteps} steps in {ms:.2f} ms ({1e3 * ms / nsteps:.2f} us/step), "
+              f"rel L2 vs exact {err:.3e}", file=sys.stderr, flush=True)
+    return res
 
 
 def bench_3d(P, I, args):
@@ -442,6 +487,7 @@ def main():
         out["stencils_stage_kernels"] = stencils
     if not args.no_msd:
         out["msd2d"] = bench_msd(P, I, args, res, npts)
+    out["soliton1d"] = bench_1d(P, I)
     if args.n3d > 0:
         out["gp3d"] = bench_3d(P, I, args)
     if args.batch_steps > 0:
