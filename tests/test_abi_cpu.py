@@ -59,3 +59,34 @@ def test_committed_corrector_weights_load():
     p, scale = K.load_weights()
     assert p.dtype == np.float32 and p.size == 32 * 9 * 8 + 32 + 32 * 9 * 32 + 32 + 2 * 9 * 32 + 2
     assert np.all(np.isfinite(p)) and 0 < scale < 1
+
+
+def test_parameter_validation_before_any_allocation():
+    """nlse_create and nlse_batch_create reject invalid problems with their documented codes before
+    touching the device, so this runs without a GPU."""
+    import numpy as np
+    import nlse_inputs as I
+    import paper_1109_1027_amd as P
+    bad = [dict(ndim=4, n=8, h=0.1, a=1.0, s=1.0),            # ndim
+           dict(ndim=2, n=1, h=0.1, a=1.0, s=1.0),            # fewer than 2 intervals
+           dict(ndim=2, n=8, h=0.0, a=1.0, s=1.0),            # h
+           dict(ndim=2, n=8, h=0.1, a=-1.0, s=1.0),           # a > 0 required
+           dict(ndim=2, n=8, h=0.1, a=1.0, s=float("nan")),   # s finite
+           dict(ndim=1, n=3, h=0.1, a=1.0, s=1.0, bc="msd")]  # 1D MSD needs n >= 4
+    for kw in bad:
+        try:
+            P.Solver(kw.pop("ndim"), kw.pop("n"), kw.pop("h"), kw.pop("a"), kw.pop("s"), stream=None, **kw)
+        except P.NLSEError as e:
+            assert e.code == -1, (e.code, e)
+        else:
+            raise AssertionError("invalid parameters accepted")
+    g3 = I.grid(3, 8, -1.0, 1.0)
+    g2 = I.grid(2, 8, -1.0, 1.0)
+    for spec, code in ((I.ProblemSpec("a", g3, 0.5, -1.0, None, np.zeros(g3.shape, complex)), -6),
+                       (I.ProblemSpec("b", g2, 0.5, -1.0, None, np.zeros(g2.shape, complex), "msd"), -6)):
+        try:
+            P.Batch([spec], prec="f32", stream=None)
+        except P.NLSEError as e:
+            assert e.code == code, (e.code, e)
+        else:
+            raise AssertionError("unsupported batch accepted")
