@@ -267,6 +267,19 @@ def bench_3d(P, I, args):
             print(f"[bench] 3D {prec} stage kernels: {res[prec]['stage_kernels']['value']:.2f} Gpt*steps/s, "
                   f"{ach_s:.0f} GB/s algorithmic ({100 * ach_s / HBM_PEAK_GBS:.1f}% of HBM peak)",
                   file=sys.stderr, flush=True)
+        if not args.no_stencils:   # Sec. 5's comparison in 3D: stage kernels, same bytes per point-step
+            sv3 = res[prec]["stage_kernels"]["tile_variant"] if "stage_kernels" in res[prec] else \
+                (0 if pairs else variant)
+            steps_x = max(args.steps3d // 4, 1)
+            for st in ("2shoc", "noncompact", "cd"):
+                ms_x = time_solver(P, spec, prec, steps_x, 3, variant=sv3, stencil=st)[0]
+                bw = BYTES_PER_POINT_STEP[prec] * npts * steps_x / (ms_x * 1e-3) / 1e9
+                res[prec].setdefault("stencils_stage_kernels", {})[st] = {
+                    "value": npts * steps_x / (ms_x * 1e-3) / 1e9, "ms_per_step": ms_x / steps_x,
+                    "algorithmic_gbs": bw, "hbm_frac": bw / HBM_PEAK_GBS, "tile_variant": sv3}
+                print(f"[bench] 3D stencil {st} {prec} (stage kernels): "
+                      f"{npts * steps_x / (ms_x * 1e-3) / 1e9:.2f} Gpt*steps/s, {100 * bw / HBM_PEAK_GBS:.1f}% of HBM peak",
+                      file=sys.stderr, flush=True)
     return res
 
 

@@ -234,6 +234,30 @@ def background_ring(g: Grid, mu=1.0, s=-1.0, ring_radius=4.0):
 # Workload definitions
 # ---------------------------------------------------------------------------
 
+def smooth_random_3d(n, seed, boundary_amp=0.0):
+    """A smooth complex test field on a 3D grid of n = (nx, ny, nz) intervals over the unit
+    cube, stored [z][y][x]: four seeded plane-wave x standing-wave modes (wavenumbers 1-4 per
+    axis, amplitudes 0.2-0.5), zero on the boundary, or, with boundary_amp, seeded Gaussian
+    complex boundary values (fixed Dirichlet data).  Returns (psi, V) with the smooth
+    potential V = 0.3 (x - 0.5)^2 + 0.2 (y - 0.4)^2 + 0.1 z."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(*[np.linspace(0.0, 1.0, m + 1) for m in reversed(n)], indexing="ij")
+    psi = np.zeros(x.shape, np.complex128)
+    for _ in range(4):
+        k = rng.uniform(1.0, 4.0, 3)
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        psi += rng.uniform(0.2, 0.5) * np.exp(1j * (k[0] * 2 * np.pi * x + ph[0])) \
+            * np.cos(k[1] * 2 * np.pi * y + ph[1]) * np.cos(k[2] * 2 * np.pi * z + ph[2])
+    bnd = np.zeros(x.shape, bool)
+    bnd[0, :, :] = bnd[-1, :, :] = bnd[:, 0, :] = bnd[:, -1, :] = bnd[:, :, 0] = bnd[:, :, -1] = True
+    if boundary_amp:
+        psi[bnd] = boundary_amp * (rng.standard_normal(bnd.sum()) + 1j * rng.standard_normal(bnd.sum()))
+    else:
+        psi[bnd] = 0.0
+    V = 0.3 * (x - 0.5) ** 2 + 0.2 * (y - 0.4) ** 2 + 0.1 * z
+    return psi, V
+
+
 @dataclasses.dataclass
 class ProblemSpec:
     """One NLSE problem: grid, coefficients, potential, initial field, boundary rule."""

@@ -124,10 +124,11 @@ static bool step2d_ok(const nlse_ctx *c)
 }
 
 // 3D variants: [0, stage3d_variants()) the stage kernels, the rest the two-stage pairs
-// (Dirichlet, 32-bit offsets).
+// (2SHOC, Dirichlet, 32-bit offsets).
 static bool step3d_ok(const nlse_ctx *c)
 {
-    return c->p.ndim == 3 && c->p.bc == NLSE_BC_DIRICHLET && c->L.total < (int64_t(1) << 31);
+    return c->p.ndim == 3 && c->stencil == NLSE_STENCIL_2SHOC && c->p.bc == NLSE_BC_DIRICHLET &&
+           c->L.total < (int64_t(1) << 31);
 }
 
 static int variant_count(const nlse_ctx *c)
@@ -225,10 +226,12 @@ int nlse_set_stencil(nlse_ctx *c, int32_t stencil)
 {
     if (!c) return fail(NLSE_E_INVAL, "NULL context");
     if (stencil < NLSE_STENCIL_2SHOC || stencil > NLSE_STENCIL_CD) return fail(NLSE_E_INVAL, "unknown stencil");
-    if (stencil != NLSE_STENCIL_2SHOC && c->p.ndim != 2)
-        return fail(NLSE_E_UNSUPPORTED, "the alternative stencils are implemented in 2D only");
+    if (stencil != NLSE_STENCIL_2SHOC && c->p.ndim == 1)
+        return fail(NLSE_E_UNSUPPORTED, "the alternative stencils are implemented in 2D and 3D only");
+    if (stencil != NLSE_STENCIL_2SHOC && c->p.bc != NLSE_BC_DIRICHLET)
+        return fail(NLSE_E_UNSUPPORTED, "the alternative stencils are implemented for Dirichlet boundaries only");
     c->stencil = stencil;
-    if (c->variant >= variant_count(c)) c->variant = 0;   // whole-step variants are 2SHOC only
+    if (c->variant >= variant_count(c)) c->variant = 0;   // whole-step and two-stage variants are 2SHOC only
     return NLSE_OK;
 }
 

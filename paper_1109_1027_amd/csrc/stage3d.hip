@@ -26,6 +26,13 @@
 // Dirichlet constants of launch_boundary_d, or under MSD the values msd.hip forms
 // from the stage's input before each launch; see stage2d.hip for why the per-axis
 // and single-storage forms then coincide.
+//
+// Alternative Laplacians for comparison (ST, from StageArgs::stencil): the
+// non-compact fourth-order 13-point cross (Sec. 2.3: the 3D counterpart of
+// Eq. 2dnonhoc), one five-point difference per axis with odd-reflection ghosts
+// 2 Psi_b - Psi_{b+-1} one node beyond the boundary, read from the same plane
+// buffer (two-node halo) and column queue (z-2..z+2); and the second-order
+// central difference D^x + D^y + D^z.  Neither needs the D halos in LDS.
 #include "kernels.h"
 #include "point.h"
 
@@ -34,7 +41,7 @@ namespace nlse {
 template <typename T, typename U> struct same3_t { static constexpr bool v = false; };
 template <typename T> struct same3_t<T, T> { static constexpr bool v = true; };
 
-template <typename IN, typename R, typename M, int TYB, int TZ, int STAGE>
+template <typename IN, typename R, typename M, int TYB, int TZ, int STAGE, int ST>
 __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tiles_x, int tiles_y)
 {
     constexpr int W = 64, NT = 64 * TYB;
@@ -133,8 +140,11 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
     for (int k = 0; k < 5; ++k) q[k] = ldp(z0 - 2 + k, cidx, col_ok);
     C<R> hx = ldp(z0, hx_idx, hx_ok), hy = ldp(z0, hy_idx, hy_ok);
     Ops ops = ld_ops(z0);
-    C<R> dzm = dz_at(z0 - 1, q[0], q[1], q[2]);
-    C<R> dz0 = dz_at(z0, q[1], q[2], q[3]);
+    C<R> dzm = czero<R>(), dz0 = czero<R>();
+    if constexpr (ST != 1) {
+        dzm = dz_at(z0 - 1, q[0], q[1], q[2]);
+        dz0 = dz_at(z0, q[1], q[2], q[3]);
+    }
 
     for (int zi = 0; zi < TZ; ++zi) {
         const int z = z0 + zi;
@@ -148,24 +158,43 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
             nhy = ldp(z + 1, hy_idx, hy_ok);
             nops = ld_ops(z + 1);
         }
-        const C<R> dzp = dz_at(z + 1, q[2], q[3], q[4]);
+        C<R> dzp = czero<R>();
+        if constexpr (ST != 1) dzp = dz_at(z + 1, q[2], q[3], q[4]);
         sp[ty + 2][tx + 2] = q[2];
         if (hx_role) sp[hx_pos_r][hx_pos_c] = hx;
         if (hy_role) sp[hy_pos_r][hy_pos_c] = hy;
         __syncthreads();
-        C<R> dx = d2(sp[ty + 2][tx + 1], q[2], sp[ty + 2][tx + 3]);
-        C<R> dy = d2(sp[ty + 1][tx + 2], q[2], sp[ty + 3][tx + 2]);
-        if (xface) dx = unscaled<R>(DBx[fx + z * (ny + 1) + y], lc.h2);
-        if (yface) dy = unscaled<R>(DBy[fy + z * (nx + 1) + x], lc.h2);
-        sdx[ty][tx + 1] = dx;
-        sdy[ty + 1][tx] = dy;
-        if (hdx_role) {
+        C<R> dx = czero<R>(), dy = czero<R>(), lapnc = czero<R>();
+        if constexpr (ST != 1) {
+            dx = d2(sp[ty + 2][tx + 1], q[2], sp[ty + 2][tx + 3]);
+            dy = d2(sp[ty + 1][tx + 2], q[2], sp[ty + 3][tx + 2]);
+        } else if (upd_col) {   // the plane buffer is read before the barrier that lets it be rewritten
+            const C<R> u = q[2];
+            const R i12h2 = (R)(A.c.ih2 / 12.0);
+            const C<R> xm1 = sp[ty + 2][tx + 1], xp1 = sp[ty + 2][tx + 3];
+            const C<R> xm2 = x == 1 ? ghost<R>(xm1, u) : sp[ty + 2][tx];
+            const C<R> xp2 = x == nx - 1 ? ghost<R>(xp1, u) : sp[ty + 2][tx + 4];
+            const C<R> ym1 = sp[ty + 1][tx + 2], yp1 = sp[ty + 3][tx + 2];
+            const C<R> ym2 = y == 1 ? ghost<R>(ym1, u) : sp[ty][tx + 2];
+            const C<R> yp2 = y == ny - 1 ? ghost<R>(yp1, u) : sp[ty + 4][tx + 2];
+            const C<R> zm2 = z == 1 ? ghost<R>(q[1], u) : q[0];
+            const C<R> zp2 = z == nz - 1 ? ghost<R>(q[3], u) : q[4];
+            lapnc = cadd<R>(cadd<R>(d4nc<R>(xm2, xm1, u, xp1, xp2, i12h2), d4nc<R>(ym2, ym1, u, yp1, yp2, i12h2)),
+                            d4nc<R>(zm2, q[1], u, q[3], zp2, i12h2));
+        }
+        if constexpr (ST == 0) {
+            if (xface) dx = unscaled<R>(DBx[fx + z * (ny + 1) + y], lc.h2);
+            if (yface) dy = unscaled<R>(DBy[fy + z * (nx + 1) + x], lc.h2);
+            sdx[ty][tx + 1] = dx;
+            sdy[ty + 1][tx] = dy;
+        }
+        if (ST == 0 && hdx_role) {
             const int c = hdx_side ? W + 2 : 1;
             C<R> hdx = d2(sp[hdx_r + 2][c - 1], sp[hdx_r + 2][c], sp[hdx_r + 2][c + 1]);
             if (hdx_face >= 0) hdx = unscaled<R>(DBx[hdx_face * fx + z * (ny + 1) + hdx_row], lc.h2);
             sdx[hdx_r][hdx_side ? W + 1 : 0] = hdx;
         }
-        if (hdy_role) {
+        if (ST == 0 && hdy_role) {
             const int r = hdy_side ? TYB + 2 : 1;
             C<R> hdy = d2(sp[r - 1][hdy_c + 2], sp[r][hdy_c + 2], sp[r + 1][hdy_c + 2]);
             if (hdy_face >= 0) hdy = unscaled<R>(DBy[hdy_face * fy + z * (nx + 1) + hdy_col], lc.h2);
@@ -174,10 +203,17 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
         __syncthreads();
         if (upd_col) {
             const int p = z * plane + cidx;
-            const C<R> alap = lap3<R>(dx, dy, dz0, sdx[ty][tx], sdx[ty][tx + 2], sdy[ty][tx], sdy[ty + 2][tx], dzm,
-                                      dzp, lc.A76, lc.A112);
             const C<R> u = q[2];
-            const C<R> F = rhs_a<R>(alap, u, ops.vv, s);
+            C<R> F;
+            if constexpr (ST == 0) {
+                const C<R> alap = lap3<R>(dx, dy, dz0, sdx[ty][tx], sdx[ty][tx + 2], sdy[ty][tx], sdy[ty + 2][tx],
+                                          dzm, dzp, lc.A76, lc.A112);
+                F = rhs_a<R>(alap, u, ops.vv, s);
+            } else if constexpr (ST == 2) {   // a/h^2 (D^x + D^y + D^z) from the unscaled differences
+                F = rhs_a<R>(cscale<R>((R)(A.c.a * A.c.ih2), cadd<R>(cadd<R>(dx, dy), dz0)), u, ops.vv, s);
+            } else {
+                F = rhs<R>(lapnc, u, ops.vv, (R)A.c.a, s);
+            }
             if (STAGE == 1) {
                 const C<M> base = in_is_r ? cvt<M, R>(u) : ops.pn;
                 K[p] = F;
@@ -202,37 +238,48 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
     }
 }
 
-template <typename IN, typename R, typename M, int TYB, int TZ, int STAGE>
+template <typename IN, typename R, typename M, int TYB, int TZ, int STAGE, int ST>
 static hipError_t launch3(const StageArgs &a, hipStream_t st)
 {
     const int64_t tiles_x = (a.L.nx - 1 + 63) / 64;
     const int64_t tiles_y = (a.L.ny - 1 + TYB - 1) / TYB;
     const int64_t tiles_z = (a.L.nz - 1 + TZ - 1) / TZ;
     const int64_t blocks = tiles_x * tiles_y * tiles_z;
-    hipLaunchKernelGGL((stage3d_kernel<IN, R, M, TYB, TZ, STAGE>), dim3((unsigned)blocks), dim3(64 * TYB), 0, st, a,
+    hipLaunchKernelGGL((stage3d_kernel<IN, R, M, TYB, TZ, STAGE, ST>), dim3((unsigned)blocks), dim3(64 * TYB), 0, st, a,
                        (int)tiles_x, (int)tiles_y);
     return hipGetLastError();
 }
 
-template <typename IN, typename R, typename M, int TYB, int TZ>
+template <typename IN, typename R, typename M, int TYB, int TZ, int ST>
 static hipError_t launch3s(const StageArgs &a, hipStream_t st)
 {
     switch (a.stage) {
-    case 1: return launch3<IN, R, M, TYB, TZ, 1>(a, st);
-    case 2: return launch3<IN, R, M, TYB, TZ, 2>(a, st);
-    case 3: return launch3<IN, R, M, TYB, TZ, 3>(a, st);
-    default: return launch3<IN, R, M, TYB, TZ, 4>(a, st);
+    case 1: return launch3<IN, R, M, TYB, TZ, 1, ST>(a, st);
+    case 2: return launch3<IN, R, M, TYB, TZ, 2, ST>(a, st);
+    case 3: return launch3<IN, R, M, TYB, TZ, 3, ST>(a, st);
+    default: return launch3<IN, R, M, TYB, TZ, 4, ST>(a, st);
+    }
+}
+
+template <typename IN, typename R, typename M, int ST>
+static hipError_t launch3t(const StageArgs &a, hipStream_t st)
+{
+    switch (a.variant) {
+    case 0: return launch3s<IN, R, M, 4, 32, ST>(a, st);
+    case 1: return launch3s<IN, R, M, 4, 64, ST>(a, st);
+    case 2: return launch3s<IN, R, M, 8, 32, ST>(a, st);
+    case 3: return launch3s<IN, R, M, 4, 16, ST>(a, st);
+    default: return hipErrorInvalidValue;
     }
 }
 
 template <typename IN, typename R, typename M>
 static hipError_t launch3v(const StageArgs &a, hipStream_t st)
 {
-    switch (a.variant) {
-    case 0: return launch3s<IN, R, M, 4, 32>(a, st);
-    case 1: return launch3s<IN, R, M, 4, 64>(a, st);
-    case 2: return launch3s<IN, R, M, 8, 32>(a, st);
-    case 3: return launch3s<IN, R, M, 4, 16>(a, st);
+    switch (a.stencil) {
+    case 0: return launch3t<IN, R, M, 0>(a, st);
+    case 1: return launch3t<IN, R, M, 1>(a, st);
+    case 2: return launch3t<IN, R, M, 2>(a, st);
     default: return hipErrorInvalidValue;
     }
 }

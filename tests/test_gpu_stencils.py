@@ -1,4 +1,4 @@
-"""The alternative 2D Laplacians of the stage kernel (nlse_set_stencil) against the oracle.
+"""The alternative 2D and 3D Laplacians of the stage kernels (nlse_set_stencil) against the oracle.
 
 The non-compact fourth-order stencil and the second-order CD are what 2SHOC is compared with
 (Sec. 2.1, Sec. 5).  The oracle implements both (lap="noncompact" with odd-reflection ghosts
@@ -88,9 +88,70 @@ def test_stencil_variants_bitwise_and_api(gpu, stencil):
     assert s0.variant_count() == n_all
 
 
-def test_stencil_unsupported_outside_2d(gpu):
+@pytest.mark.parametrize("stencil", ["noncompact", "cd"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+@pytest.mark.parametrize("n", [(5, 5, 5), (40, 40, 40), (61, 23, 9), (70, 18, 33), (2, 3, 2)])
+def test_stencil3d_parity_with_oracle(gpu, orc, stencil, prec, n):
+    """3D stage kernels: 13-point non-compact cross and 7-point CD, random Dirichlet values,
+    ragged tiles in every direction, grids smaller than a tile."""
+    psi, V = I.smooth_random_3d(n, 7, boundary_amp=0.3)
+    h = 1.0 / max(n)
+    dt = 0.4 * orc.Problem(3, n, h, 0.5, -1.0, V).max_dt(psi)
+    ref = orc.Problem(3, n, h, 0.5, -1.0, V, lap=stencil).rk4(psi, 10, dt)
+    s = gpu.Solver(3, n, h, 0.5, -1.0, V, "dirichlet", prec)
+    s.stencil = stencil
+    s.set_field(psi.astype(s.dtype))
+    say(f"[case] 3D {stencil} {prec} n={n}, 10 steps")
+    s.step(10, dt)
+    e = rel(s.get_field(), ref)
+    s.close()
+    say(f"[result] 3D {stencil} {prec} n={n}: rel L2 {e:.3e}")
+    assert e <= TOL[prec]
+
+
+@pytest.mark.parametrize("stencil", ["noncompact", "cd"])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_stencil3d_variants_bitwise_and_api(gpu, stencil, prec):
+    n = (66, 37, 70)
+    psi, V = I.smooth_random_3d(n, 9, boundary_amp=0.3)
+    h = 1.0 / 70
+    s0 = gpu.Solver(3, n, h, 0.5, -1.0, V, "dirichlet", prec)
+    n_all = s0.variant_count()
+    s0.variant = n_all - 1                 # a two-stage variant
+    s0.stencil = stencil
+    assert s0.variant == 0 and s0.variant_count() == 4
+    with pytest.raises(gpu.NLSEError):
+        s0.variant = 4
+    s0.stencil = "2shoc"
+    assert s0.variant_count() == n_all
+    s0.close()
+    outs = []
+    for v in range(4):
+        s = gpu.Solver(3, n, h, 0.5, -1.0, V, "dirichlet", prec)
+        s.stencil = stencil
+        s.set_field(psi.astype(s.dtype))
+        s.variant = v
+        assert s.launches_per_step() == 4
+        say(f"[case] 3D {stencil} {prec} variant {v}, 5 steps")
+        s.step(5, 0.4 * s.max_dt())
+        outs.append(s.get_field())
+        s.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_stencil_unsupported_in_1d_and_under_msd(gpu):
     sp1 = I.config_soliton_1d(256)
     s = gpu.Solver.from_spec(sp1)
     with pytest.raises(gpu.NLSEError):
         s.stencil = "cd"
     assert s.stencil == "2shoc"
+    s.close()
+    for dim in (2, 3):
+        g = I.grid(dim, 20, -8.0, 8.0)
+        s = gpu.Solver(dim, 20, g.h, 0.5, -1.0, None, "msd", "f32")
+        for name in ("noncompact", "cd"):
+            with pytest.raises(gpu.NLSEError):
+                s.stencil = name
+        assert s.stencil == "2shoc"
+        s.close()

@@ -29,27 +29,6 @@ def say(*a):
     sys.stdout.flush()
 
 
-def smooth_field(n, seed, boundary_amp=0.0):
-    """A smooth complex field on (n[2]+1, n[1]+1, n[0]+1) nodes, optionally with random
-    (fixed) Dirichlet values."""
-    rng = np.random.default_rng(seed)
-    z, y, x = np.meshgrid(*[np.linspace(0.0, 1.0, m + 1) for m in reversed(n)], indexing="ij")
-    psi = np.zeros(x.shape, np.complex128)
-    for _ in range(4):
-        k = rng.uniform(1.0, 4.0, 3)
-        ph = rng.uniform(0, 2 * np.pi, 3)
-        psi += rng.uniform(0.2, 0.5) * np.exp(1j * (k[0] * 2 * np.pi * x + ph[0])) \
-            * np.cos(k[1] * 2 * np.pi * y + ph[1]) * np.cos(k[2] * 2 * np.pi * z + ph[2])
-    bnd = np.zeros(x.shape, bool)
-    bnd[0, :, :] = bnd[-1, :, :] = bnd[:, 0, :] = bnd[:, -1, :] = bnd[:, :, 0] = bnd[:, :, -1] = True
-    if boundary_amp:
-        psi[bnd] = boundary_amp * (rng.standard_normal(bnd.sum()) + 1j * rng.standard_normal(bnd.sum()))
-    else:
-        psi[bnd] = 0.0
-    V = 0.3 * (x - 0.5) ** 2 + 0.2 * (y - 0.4) ** 2 + 0.1 * z
-    return psi, V
-
-
 def pair_variants(s):
     out = []
     for v in range(s.variant_count()):
@@ -73,7 +52,7 @@ def run(gpu, n, h, psi, V, prec, variant, steps, dt):
 @pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
 @pytest.mark.parametrize("n", [(70, 70, 70), (61, 23, 9), (5, 4, 6), (130, 17, 40), (2, 2, 2), (3, 2, 5)])
 def test_pairs_bitwise_equal_to_stage_kernels(gpu, prec, n):
-    psi, V = smooth_field(n, 3, boundary_amp=0.3)
+    psi, V = I.smooth_random_3d(n, 3, boundary_amp=0.3)
     h = 1.0 / max(n)
     s = gpu.Solver(3, n, h, 0.5, -1.0, V, "dirichlet", prec)
     s.set_field(psi.astype(s.dtype))
@@ -110,7 +89,7 @@ def test_pairs_oracle_parity(gpu, orc, prec):
 def test_pairs_mixed_with_stage_kernels(gpu):
     """Switching between pair and stage variants mid-run (the master buffers swap) changes nothing."""
     n = (66, 31, 20)
-    psi, V = smooth_field(n, 5)
+    psi, V = I.smooth_random_3d(n, 5)
     h = 1.0 / 66
     s = gpu.Solver(3, n, h, 0.5, -1.0, V, "dirichlet", "f32")
     s.set_field(psi.astype(np.complex64))

@@ -166,6 +166,37 @@ def test_cd_is_second_difference(orc):
     np.testing.assert_allclose(out[1:-1, 1:-1], ref, rtol=1e-13, atol=1e-13)
 
 
+@pytest.mark.parametrize("dim,n", [(2, 9), (3, 7)])
+def test_cd_quartic_closed_form(orc, dim, n):
+    """The second difference of x^4 is 12 x^2 + 2 h^2 exactly, so CD(sum_a x_a^4) =
+    12 |r|^2 + 2 d h^2 at every interior node (catches a dropped axis or a wrong scale)."""
+    h = 0.25
+    idx = np.indices((n + 1,) * dim).astype(float) * h - 0.6   # [z][y][x] order, any origin
+    f = np.sum(idx ** 4, axis=0) * (1.0 - 0.5j)
+    out = orc.Problem(dim, n, h, 1.0, 0.0, lap="cd").laplacian(f)
+    ref = (12.0 * np.sum(idx ** 2, axis=0) + 2.0 * dim * h * h) * (1.0 - 0.5j)
+    np.testing.assert_allclose(inner(out, dim, 1), inner(ref, dim, 1), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 8), (3, 6)])
+def test_noncompact_odd_ghost_closed_form(orc, dim, n):
+    """Odd reflection ghosts with non-zero boundary values.  With x_a measured from the lower
+    boundary, the ghost of x^2 is 2 f(0) - f(h) = -h^2 below and the true value - 2 h^2
+    above, so the five-point difference gives 2 deep inside and 26/12 next to either face of
+    that axis; linear terms and constants reflect exactly.  Hence for
+    f = sum_a (x_a^2 + c_a x_a) + c0:  Lap = 2 d + (2/12) (number of axes on which the node
+    is next to a face)."""
+    h = 0.3
+    ii = np.indices((n + 1,) * dim)
+    xs = ii.astype(float) * h
+    c = np.array([0.7, -1.1, 0.4][:dim])
+    f = (np.sum(xs ** 2, axis=0) + np.tensordot(c, xs, axes=1) + 2.5) * (0.8 + 0.3j)
+    out = orc.Problem(dim, n, h, 1.0, 0.0, lap="noncompact").laplacian(f)
+    near = np.sum((ii == 1) | (ii == n - 1), axis=0)
+    ref = (2.0 * dim + (2.0 / 12.0) * near) * (0.8 + 0.3j)
+    np.testing.assert_allclose(inner(out, dim, 1), inner(ref, dim, 1), rtol=1e-11, atol=1e-11)
+
+
 def test_3d_edge_neighbours_decoding(orc):
     """The single-storage 3D step 2 touches exactly the 6 face and 12 edge neighbours:
     its response to a delta equals the 13-point non-compact stencil (no corner terms)."""
