@@ -194,6 +194,49 @@ def cpu_baseline(spec, budget_s=12.0, budget_1core_s=6.0):
             "soliton1d_full_run_s_1thread": el_1d, "soliton1d_steps": n1}
 
 
+def cpu_baseline_3d(n3d, budget_s=15.0, cap=5):
+    """The FP64 oracle on config 3's full grid: up to `cap` RK4 steps on all host threads."""
+    import oracle
+    import nlse_inputs as I
+    spec = I.config_gp3d(n=n3d)
+    P = oracle.Problem.from_spec(spec)
+    dt = 0.5 * P.max_dt(spec.psi0)
+    psi, steps, t0 = spec.psi0, 0, time.perf_counter()
+    while True:
+        psi = P.rk4(psi, 1, dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= cap:
+            break
+    cores = oracle.threads()
+    return {"value": spec.interior_points * steps / el / 1e9, "unit": "Gpt·steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{steps} RK4 steps of the FP64 oracle on the full {n3d + 1}^3 grid ({el:.1f} s, {cores} threads)"}
+
+
+def cpu_baseline_batch(steps=10, every1d=16, every2d=8):
+    """The FP64 oracle on a fixed sample of the batched workload's instances (every 16th 1D and
+    every 8th 2D instance), `steps` RK4 steps each at 0.5 x its own bound, one after another."""
+    import oracle
+    import nlse_inputs as I
+    specs = I.batch_instances()
+    sample = [sp for i, sp in enumerate(specs) if sp.dim == 1 and i % every1d == 0]
+    sample += [sp for i, sp in enumerate(x for x in specs if x.dim == 2) if i % every2d == 0]
+    runs = []
+    for sp in sample:
+        P = oracle.Problem.from_spec(sp)
+        runs.append((P, sp.psi0, 0.5 * P.max_dt(sp.psi0), sp.interior_points))
+    t0 = time.perf_counter()
+    for P, psi0, dt, _ in runs:
+        P.rk4(psi0, steps, dt)
+    el = time.perf_counter() - t0
+    pts = sum(r[3] for r in runs) * steps
+    n1 = sum(1 for sp in sample if sp.dim == 1)
+    return {"value": pts / el / 1e9, "unit": "Gpt·steps/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{n1} 1D + {len(sample) - n1} 2D instances of the batched workload (every {every1d}th / "
+                      f"{every2d}th), {steps} RK4 steps each ({el:.1f} s, {oracle.threads()} threads)"}
+
+
 def bench_1d(P, I):
     """Config 1 (1D bright soliton, 1025 nodes, to t = 10): one launch of the on-chip solver for
     the whole run; wall time and the distance to the exact solution."""
@@ -510,6 +553,10 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec)
+        if args.n3d > 0:
+            out["cpu_baseline"]["gp3d"] = cpu_baseline_3d(args.n3d)
+        if args.batch_steps > 0:
+            out["cpu_baseline"]["batch"] = cpu_baseline_batch()
     print(json.dumps(out), flush=True)
 
 

@@ -109,6 +109,38 @@ def test_2d_full_size_two_steps(gpu, orc):
         assert rel(g, ref) <= TOL[prec], (prec, rel(g, ref))
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+def test_2d_config2_full_run_vs_stored_oracle(gpu, prec):
+    """The whole benchmark run: 2049^2 nodes, 2000 RK4 steps at dt = 0.5 k_max, in the launch
+    configuration the benchmark times (the autotuner's choice), against the FP64 oracle's state
+    sampled at 545 nodes (tests/golden/make_gp2d_full_run.py writes it from the oracle alone),
+    plus its mass and energy."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "gp2d_2048_2000steps.json")
+    with open(path) as f:
+        gold = json.load(f)
+    sp = I.config_gp2d(n=gold["n"])
+    s = gpu.Solver.from_spec(sp, prec=prec)
+    s.set_field(sp.psi0)
+    v = s.autotune(reps=5)
+    say(f"[case] 2049^2 {prec} variant {v}, {gold['steps']} steps at dt {gold['dt']:.9g}")
+    s.step(gold["steps"], gold["dt"])
+    g = np.asarray(s.get_field(), np.complex128)
+    mass, energy = s.mass(), s.energy()
+    s.close()
+    iy, ix = np.array(gold["nodes"]).T
+    ref = np.array(gold["re"]) + 1j * np.array(gold["im"])
+    got = g[iy, ix]
+    e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    em = abs(mass - gold["mass"]) / gold["mass"]
+    ee = abs(energy - gold["energy"]) / abs(gold["energy"])
+    say(f"[result] 2049^2 {prec} full run: sampled rel L2 {e:.3e}, mass {em:.3e}, energy {ee:.3e}")
+    assert e <= TOL[prec]
+    assert em <= (1e-12 if prec == "f64" else 1e-5)
+    assert ee <= (1e-10 if prec == "f64" else 1e-4)
+
+
 # ------------------------------------------------------------------- 1D --
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
