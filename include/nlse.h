@@ -69,8 +69,8 @@ typedef enum {
                               closest interior node: the normal neighbour on a face, the
                               diagonal one on an edge or corner (2D/3D; Sec. 3.2 says the rule
                               carries over to several dimensions, the corner choice is ours).
-                              1D needs n >= 4 intervals.  2D/3D run the stage kernels with two
-                              small boundary launches per stage */
+                              1D needs n >= 4 intervals.  2D/3D run the stage kernels with one
+                              small boundary launch before each stage */
 } nlse_bc;
 
 typedef enum {
@@ -142,10 +142,10 @@ void nlse_destroy(nlse_ctx *c);
 const char *nlse_last_error(void);
 
 /* Number of kernel launches one RK4 step enqueues for this context with its current
- * variant: 4 for the 2D/3D stage kernels (12 under MSD: face values and boundary update
- * around each stage), 1 for the 2D whole-step kernels and 2 for the 3D two-stage kernels
- * (Dirichlet only); 1D contexts
- * advance all steps in one launch and report 0.  For throughput accounting. */
+ * variant: 4 for the 2D/3D stage kernels (8 under MSD: a boundary launch, face values
+ * and boundary nodes, before each stage), 1 for the 2D whole-step kernels and 2 for the
+ * 3D two-stage kernels (Dirichlet only); 1D contexts advance all steps in one launch and
+ * report 0.  For throughput accounting. */
 int nlse_launches_per_step(const nlse_ctx *c);
 
 /* Kernel variants.  2D: 0-2 are the stage kernels (one launch per RK4 stage, tiles of

@@ -13,7 +13,7 @@ enum Prec { P_F64 = 0, P_F32 = 1, P_MIXED = 2 };
 //   stage 3: in = Psi_tmp          K += 2F        out = Psi^n + k F
 //   stage 4: in = Psi_tmp          Psi^n = Psi^n + (k/6)(K + F)
 // Only interior nodes are written; boundary nodes of every stage field hold the
-// fixed Dirichlet values (under MSD, launch_msd_update writes them).
+// fixed Dirichlet values (under MSD, launch_msd_stage writes them).
 struct StageArgs {
     const void *in;     // stencil input field
     void *out;          // stage output (stages 1-3)
@@ -25,7 +25,7 @@ struct StageArgs {
     Coeffs c;
     int stage;
     int variant;        // tile-shape variant (see stage2d_variants / stage3d_variants)
-    int stencil;        // 2D: 0 2SHOC, 1 non-compact fourth order, 2 second-order CD
+    int stencil;        // 0 2SHOC, 1 non-compact fourth order, 2 second-order CD (2D/3D)
 };
 
 // 2D fused stage kernel: per-axis 2SHOC, one 64-column x RW-row tile per wave.
@@ -92,13 +92,14 @@ hipError_t launch_boundary_d(Prec prec, const void *psin, const void *V, const L
 
 // MSD boundary in 2D/3D (msd.hip).  Face values D^a_b of the per-axis form from the MSD
 // step-1 closure of the field `in` (master = true: `in` is the master field, else a
-// stage field); then, after a stage's interior launch, F_b and the stage's RK4 array
-// operations on every boundary node (same StageArgs as the interior launch, whose face
-// values must come from launch_msd_faces on a.in); and the bound's boundary term
-// max (h^2/a)|F_{b-1}/Psi_{b-1}| of the master field into dev_out (face values first).
+// stage field) into DB; the boundary part of one RK4 stage, launched before the
+// interior launch with the same StageArgs: the face values of a.in into DB, and F_b
+// with the stage's RK4 array operations on every boundary node; and the bound's
+// boundary term max (h^2/a)|F_{b-1}/Psi_{b-1}| of the master field into dev_out (face
+// values first).
 hipError_t launch_msd_faces(Prec prec, bool master, const void *in, const void *V, const Layout &L,
                             const Coeffs &c, void *const DB[3], hipStream_t st);
-hipError_t launch_msd_update(Prec prec, const StageArgs &a, hipStream_t st);
+hipError_t launch_msd_stage(Prec prec, const StageArgs &a, void *const DB[3], hipStream_t st);
 hipError_t launch_msd_bound(Prec prec, const void *psin, const void *V, const void *const DB[3], const Layout &L,
                             const Coeffs &c, double h2a, double *dev_out, hipStream_t st);
 

@@ -14,13 +14,15 @@
 // a, the value D^a_b = Lap_b - (second differences along the face), the closure
 // under which the per-axis form equals the single-storage one.  Under Dirichlet
 // those values are constants; under MSD they follow the field, so every RK4 stage
-// runs three launches:
-//   1. msd_face_kernel    D^a_b on every face node from the stage's input field;
-//   2. the interior stage kernel (unchanged: it reads the face values);
-//   3. msd_update_kernel  F_b from F_{b-1}, recomputed from the same input and face
-//      values (interior first, boundary second), and the stage's RK4 array
-//      operations on the boundary nodes.
-// The boundary work is O(n^(d-1)) against the interior's O(n^d).
+// runs two launches:
+//   1. msd_stage_kernel   one thread per boundary node: D^a_b on the face nodes from
+//      the stage's input field, for the interior launch; and F_b from F_{b-1}
+//      (interior first, boundary second), with F_{b-1} recomputed from the same input
+//      and face values formed on the spot, then the stage's RK4 array operations on
+//      the boundary node.  Neither part reads what the interior launch writes.
+//   2. the interior stage kernel (unchanged: it reads the face values).
+// The boundary work is O(n^(d-1)) against the interior's O(n^d).  msd_face_kernel
+// alone serves the bound and the energy.
 #include "kernels.h"
 #include "point.h"
 
@@ -113,18 +115,55 @@ struct Field {
     }
 };
 
-// The face value D^a read by the interior kernels at node r (r on the face normal to a).
-template <typename R>
-__device__ __forceinline__ C<R> face_value(const Layout &L, const C<R> *const DB[3], int a, const Node &r)
+// The face value D^a_b at the face node b (normal to a, on no other face): the MSD step-1
+// value of Eq. msdbc_lap, from the full step-1 value at b-1, minus the second differences
+// along the face.
+template <typename IN, typename R>
+__device__ __forceinline__ C<R> face_closure(const Field<IN, R> &f, const Coeffs &cf, int a, const Node &b)
 {
-    const int side = r.at(a) == 0 ? 0 : 1;
-    return DB[a][side * face_size(L, a) + face_index(L, a, r)];
+    const Layout &L = f.L;
+    const int side = b.at(a) == 0 ? 0 : 1;
+    const R ih2 = (R)cf.ih2, s = (R)cf.s;
+    const Node q = step(b, a, side ? -1 : 1);
+    const C<R> ub = f.psi(b), uq = f.psi(q);
+    C<R> Dq = czero<R>();   // the full step-1 value at b-1 (Eqs. 2d2shocs1, 3d2shocs)
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        if (t < L.dim) Dq = cadd<R>(Dq, f.d2a(q, t, ih2));
+    const R den = uq.x * uq.x + uq.y * uq.y;
+    const R ratio = den != R(0) ? (Dq.x * uq.x + Dq.y * uq.y) / den : R(0);
+    const R fac = ratio + (nonlin<R>(uq, f.pot(q), s) - nonlin<R>(ub, f.pot(b), s)) * (R)cf.ia;
+    C<R> Db = mk<R>(fac * ub.x, fac * ub.y);   // Lap_b
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        if (t < L.dim && t != a) Db = csub<R>(Db, f.d2a(b, t, ih2));
+    return Db;
 }
+
+// Face values as the interior kernels read them: from the face arrays ...
+template <typename R>
+struct StoredFaces {
+    const C<R> *DB[3];
+    Layout L;
+    __device__ __forceinline__ C<R> operator()(int a, const Node &r) const
+    {
+        const int side = r.at(a) == 0 ? 0 : 1;
+        return DB[a][side * face_size(L, a) + face_index(L, a, r)];
+    }
+};
+
+// ... or formed from the field on the spot (while another thread may be writing the arrays).
+template <typename IN, typename R>
+struct DirectFaces {
+    Field<IN, R> f;
+    Coeffs cf;
+    __device__ __forceinline__ C<R> operator()(int a, const Node &r) const { return face_closure<IN, R>(f, cf, a, r); }
+};
 
 // F at the interior node q, per-axis 2SHOC (Eqs. 2d2shocMs1-2, 3d2shocMs1-2) with the face
 // values where q's neighbour along an axis is a boundary node.
-template <typename IN, typename R>
-__device__ C<R> interior_F(const Field<IN, R> &f, const C<R> *const DB[3], const Coeffs &cf, const Node &q)
+template <typename IN, typename R, typename Faces>
+__device__ C<R> interior_F(const Field<IN, R> &f, const Faces &face_value, const Coeffs &cf, const Node &q)
 {
     const R ih2 = (R)cf.ih2, c76 = (R)cf.c76, c112 = (R)cf.c112;
     C<R> dc[3], dl[3], dr[3];
@@ -134,8 +173,8 @@ __device__ C<R> interior_F(const Field<IN, R> &f, const C<R> *const DB[3], const
         if (a >= f.L.dim) continue;
         dc[a] = f.d2a(q, a, ih2);
         const Node lo = step(q, a, -1), hi = step(q, a, 1);
-        dl[a] = lo.at(a) == 0 ? face_value<R>(f.L, DB, a, lo) : f.d2a(lo, a, ih2);
-        dr[a] = hi.at(a) == ext(f.L, a) ? face_value<R>(f.L, DB, a, hi) : f.d2a(hi, a, ih2);
+        dl[a] = lo.at(a) == 0 ? face_value(a, lo) : f.d2a(lo, a, ih2);
+        dr[a] = hi.at(a) == ext(f.L, a) ? face_value(a, hi) : f.d2a(hi, a, ih2);
     }
     C<R> lap;
     if (f.L.dim == 2) {
@@ -168,22 +207,8 @@ __global__ void msd_face_kernel(Field<IN, R> f, Coeffs cf, C<R> *DBx, C<R> *DBy,
 #pragma unroll
     for (int t = 0; t < 3; ++t)
         if (t != a && on_bnd(L, b, t)) return;   // edge / corner: never read by the stage kernels
-    const R ih2 = (R)cf.ih2, s = (R)cf.s;
-    const Node q = step(b, a, side ? -1 : 1);
-    const C<R> ub = f.psi(b), uq = f.psi(q);
-    C<R> Dq = czero<R>();   // the full step-1 value at b-1 (Eqs. 2d2shocs1, 3d2shocs)
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-        if (t < L.dim) Dq = cadd<R>(Dq, f.d2a(q, t, ih2));
-    const R den = uq.x * uq.x + uq.y * uq.y;
-    const R ratio = den != R(0) ? (Dq.x * uq.x + Dq.y * uq.y) / den : R(0);
-    const R fac = ratio + (nonlin<R>(uq, f.pot(q), s) - nonlin<R>(ub, f.pot(b), s)) * (R)cf.ia;
-    C<R> Db = mk<R>(fac * ub.x, fac * ub.y);   // Lap_b
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-        if (t < L.dim && t != a) Db = csub<R>(Db, f.d2a(b, t, ih2));
     C<R> *dst = a == 0 ? DBx : a == 1 ? DBy : DBz;
-    dst[side * face_size(L, a) + fi] = Db;
+    dst[side * face_size(L, a) + fi] = face_closure<IN, R>(f, cf, a, b);
 }
 
 template <typename IN, typename R>
@@ -216,7 +241,7 @@ __device__ __forceinline__ bool owner(const Layout &L, const Node &b, int a)
 }
 
 template <typename IN, typename R, typename M>
-__global__ void msd_update_kernel(Field<IN, R> f, StageArgs A)
+__global__ void msd_stage_kernel(Field<IN, R> f, StageArgs A, C<R> *DBx, C<R> *DBy, C<R> *DBz)
 {
     const int a = blockIdx.y, side = blockIdx.z;
     const Layout &L = f.L;
@@ -224,11 +249,19 @@ __global__ void msd_update_kernel(Field<IN, R> f, StageArgs A)
     const int64_t fi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (fi >= face_size(L, a)) return;
     const Node b = face_node(L, a, side, fi);
+    bool face = true;   // on no other face: the interior launch reads its D^a_b
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        if (t != a && on_bnd(L, b, t)) face = false;
+    const DirectFaces<IN, R> faces{f, A.c};
+    if (face) {
+        C<R> *dst = a == 0 ? DBx : a == 1 ? DBy : DBz;
+        dst[side * face_size(L, a) + fi] = faces(a, b);
+    }
     if (!owner(L, b, a)) return;
-    const C<R> *const DB[3] = {(const C<R> *)A.DB[0], (const C<R> *)A.DB[1], (const C<R> *)A.DB[2]};
     const Node q = inner(L, b);
     const C<R> uq = f.psi(q), ub = f.psi(b);
-    const R w = phase_rate<R>(interior_F<IN, R>(f, DB, A.c, q), uq);
+    const R w = phase_rate<R>(interior_F<IN, R>(f, faces, A.c, q), uq);
     const C<R> F = mk<R>(-w * ub.y, w * ub.x);
     const int64_t p = L.idx(b.x, b.y, b.z);
     const R ck = (R)A.c.ck;
@@ -248,7 +281,7 @@ __global__ void msd_update_kernel(Field<IN, R> f, StageArgs A)
 }
 
 template <typename IN, typename R, typename M>
-static hipError_t launch_update(const StageArgs &A, hipStream_t st)
+static hipError_t launch_stage_bnd(const StageArgs &A, void *const DB[3], hipStream_t st)
 {
     const Layout &L = A.L;
     int64_t maxf = 1;
@@ -260,7 +293,8 @@ static hipError_t launch_update(const StageArgs &A, hipStream_t st)
     }
     Field<IN, R> f{(const C<IN> *)A.in, (const R *)A.V, L};
     dim3 grid((unsigned)((maxf + 255) / 256), (unsigned)L.dim, 2);
-    hipLaunchKernelGGL((msd_update_kernel<IN, R, M>), grid, dim3(256), 0, st, f, A);
+    hipLaunchKernelGGL((msd_stage_kernel<IN, R, M>), grid, dim3(256), 0, st, f, A, (C<R> *)DB[0], (C<R> *)DB[1],
+                       (C<R> *)DB[2]);
     return hipGetLastError();
 }
 
@@ -277,12 +311,12 @@ __global__ void msd_bound_kernel(Field<IN, R> f, Coeffs cf, const void *DB0, con
     if (fi >= face_size(L, a)) return;
     const Node b = face_node(L, a, side, fi);
     if (!owner(L, b, a)) return;
-    const C<R> *const DB[3] = {(const C<R> *)DB0, (const C<R> *)DB1, (const C<R> *)DB2};
+    const StoredFaces<R> faces{{(const C<R> *)DB0, (const C<R> *)DB1, (const C<R> *)DB2}, L};
     const Node q = inner(L, b);
     const C<R> uq = f.psi(q);
     const double den = (double)uq.x * uq.x + (double)uq.y * uq.y;
     if (den == 0.0) return;
-    const C<R> F = interior_F<IN, R>(f, DB, cf, q);
+    const C<R> F = interior_F<IN, R>(f, faces, cf, q);
     const double B = h2a * sqrt(((double)F.x * F.x + (double)F.y * F.y) / den);
     // non-negative doubles order as their bit patterns: the maximum is exact and order-free
     atomicMax(out, (unsigned long long)__double_as_longlong(B));
@@ -300,14 +334,14 @@ hipError_t launch_msd_faces(Prec prec, bool master, const void *in, const void *
     }
 }
 
-hipError_t launch_msd_update(Prec prec, const StageArgs &a, hipStream_t st)
+hipError_t launch_msd_stage(Prec prec, const StageArgs &a, void *const DB[3], hipStream_t st)
 {
     switch (prec) {
-    case P_F64: return launch_update<double, double, double>(a, st);
-    case P_F32: return launch_update<float, float, float>(a, st);
+    case P_F64: return launch_stage_bnd<double, double, double>(a, DB, st);
+    case P_F32: return launch_stage_bnd<float, float, float>(a, DB, st);
     default:
-        if (a.stage == 1) return launch_update<double, float, double>(a, st);
-        return launch_update<float, float, double>(a, st);
+        if (a.stage == 1) return launch_stage_bnd<double, float, double>(a, DB, st);
+        return launch_stage_bnd<float, float, double>(a, DB, st);
     }
 }
 

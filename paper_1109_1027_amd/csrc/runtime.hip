@@ -106,13 +106,11 @@ static hipError_t launch_stage(nlse_ctx *c, int stage, double dt, int variant)
     a.variant = variant;
     a.stencil = c->stencil;
     const bool msd = c->p.bc == NLSE_BC_MSD;
-    if (msd) {   // face values of this stage's input (Eq. msdbc_lap)
-        hipError_t e = launch_msd_faces(c->prec, stage == 1, a.in, c->V, c->L, a.c, c->DB, c->stream);
+    if (msd) {   // face values of this stage's input (Eq. msdbc_lap) and the boundary nodes (Eq. msdbc_ut)
+        hipError_t e = launch_msd_stage(c->prec, a, c->DB, c->stream);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = c->p.ndim == 2 ? launch_stage2d(c->prec, a, c->stream) : launch_stage3d(c->prec, a, c->stream);
-    if (e != hipSuccess || !msd) return e;
-    return launch_msd_update(c->prec, a, c->stream);   // boundary nodes (Eq. msdbc_ut)
+    return c->p.ndim == 2 ? launch_stage2d(c->prec, a, c->stream) : launch_stage3d(c->prec, a, c->stream);
 }
 
 // 2D variants: [0, stage2d_variants()) are the stage kernels, the rest the
@@ -382,7 +380,7 @@ int nlse_launches_per_step(const nlse_ctx *c)
     if (!c) return fail(NLSE_E_INVAL, "NULL context");
     if (c->p.ndim == 1) return 0;
     if (whole_step(c, c->variant)) return c->p.ndim == 2 ? 1 : 2;
-    return c->p.bc == NLSE_BC_MSD ? 12 : 4;   // MSD: face values, interior, boundary per stage
+    return c->p.bc == NLSE_BC_MSD ? 8 : 4;   // MSD: boundary nodes and face values, then the interior, per stage
 }
 
 int nlse_sync(nlse_ctx *c)

@@ -123,7 +123,7 @@ def test_msd_variants_bit_identical(gpu, dim):
     for v in range(nv):
         say(f"[case] msd {dim}d variant {v}")
         out, s2 = gpu_run(gpu, dim, g.n, g.h, psi, "f64", 5, dt, variant=v)
-        assert s2.launches_per_step() == 12
+        assert s2.launches_per_step() == 8
         outs.append(out)
         s2.close()
     for o in outs[1:]:
@@ -166,7 +166,7 @@ def test_msd_autotune_not_shared_with_dirichlet(gpu):
     m = gpu.Solver(2, g.n, g.h, 0.5, -1.0, None, "msd", "f32")
     m.set_field(psi.astype(np.complex64))
     v = m.autotune(reps=2)
-    assert 0 <= v < m.variant_count() and m.launches_per_step() == 12
+    assert 0 <= v < m.variant_count() and m.launches_per_step() == 8
     m.close()
 
 
