@@ -97,8 +97,10 @@ typedef struct {
 
 /* Create a context: validates params, allocates the resident device arrays
  * (Psi^n, two ping-pong stage fields, K_tot, V) and copies V.  The field is
- * zero until nlse_set_field.  Returns NLSE_E_INVAL for invalid params and
- * NLSE_E_UNSUPPORTED for a 1D field larger than the on-chip solver holds. */
+ * zero until nlse_set_field.  Returns NLSE_E_INVAL for invalid params,
+ * NLSE_E_UNSUPPORTED for a 1D field larger than the on-chip solver holds or a 3D
+ * field of 2^31 or more padded elements (the 3D kernels use 32-bit offsets; about
+ * 1290^3 nodes), and NLSE_E_NOMEM when the device arrays cannot be allocated. */
 int nlse_create(nlse_ctx **out, const nlse_params *p);
 
 /* Copy a full field (all (n+1)^ndim nodes, boundary included) into the context.

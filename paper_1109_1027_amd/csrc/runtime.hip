@@ -313,6 +313,9 @@ int nlse_create(nlse_ctx **out, const nlse_params *p)
     if (p->prec != NLSE_F64 && p->prec != NLSE_F32 && p->prec != NLSE_F32_MIXED)
         return fail(NLSE_E_INVAL, "unknown precision");
     if (p->bc == NLSE_BC_MSD && p->ndim == 1 && p->n[0] < 4) return fail(NLSE_E_INVAL, "MSD needs n >= 4 intervals");
+    double padded = 1.0;   // an upper bound of the padded element count, without integer overflow
+    for (int a = 0; a < p->ndim; ++a) padded *= (double)p->n[a] + 128.0;
+    if (padded > 0x1p50) return fail(NLSE_E_NOMEM, "field too large for any device");
 
     nlse_ctx *c = new nlse_ctx();
     c->p = *p;
@@ -326,6 +329,10 @@ int nlse_create(nlse_ctx **out, const nlse_params *p)
     if (p->ndim == 1 && c->L.nx + 1 > solve1d_max_nodes(c->prec)) {
         free_ctx(c);
         return fail(NLSE_E_UNSUPPORTED, "1D field larger than the on-chip solver holds");
+    }
+    if (p->ndim == 3 && c->L.total >= (int64_t(1) << 31)) {   // the 3D kernels' 32-bit element offsets
+        free_ctx(c);
+        return fail(NLSE_E_UNSUPPORTED, "3D field of 2^31 or more padded elements");
     }
 
     const size_t T = (size_t)c->L.total;

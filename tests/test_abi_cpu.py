@@ -80,6 +80,15 @@ def test_parameter_validation_before_any_allocation():
             assert e.code == -1, (e.code, e)
         else:
             raise AssertionError("invalid parameters accepted")
+    for args, code in (((3, 1300, 0.1, 1.0, 1.0), -6),             # 3D beyond 32-bit offsets
+                       ((3, (2000, 1000, 1200), 0.1, 1.0, 1.0), -6),
+                       ((2, 10 ** 9, 0.1, 1.0, 1.0), -4)):          # no device holds it
+        try:
+            P.Solver(*args, stream=None)
+        except P.NLSEError as e:
+            assert e.code == code, (args, e.code, e)
+        else:
+            raise AssertionError("oversized field accepted")
     g3 = I.grid(3, 8, -1.0, 1.0)
     g2 = I.grid(2, 8, -1.0, 1.0)
     for spec, code in ((I.ProblemSpec("a", g3, 0.5, -1.0, None, np.zeros(g3.shape, complex)), -6),
