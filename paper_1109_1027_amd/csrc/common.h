@@ -34,6 +34,15 @@ __device__ __forceinline__ C<R> cscale(R k, C<R> u) { return mk<R>(k * u.x, k * 
 template <typename R>
 __device__ __forceinline__ C<R> czero() { return mk<R>(R(0), R(0)); }
 
+// settle(v): an empty asm statement that reads v, so v (and the load it came from) must be
+// complete at this point.  The vector-memory wait counter covers loads and stores in issue
+// order; a marching kernel settles its prefetched values before it issues the plane's
+// stores, so that a later wait for the prefetch never waits for those stores as well.
+__device__ __forceinline__ void settle(float v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void settle(double v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void settle(const float2 &v) { asm volatile("" ::"v"(v.x), "v"(v.y)); }
+__device__ __forceinline__ void settle(const double2 &v) { asm volatile("" ::"v"(v.x), "v"(v.y)); }
+
 struct Layout {
     int dim;
     int64_t nx, ny, nz;   // intervals per axis (0 for unused axes)

@@ -201,30 +201,10 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
             sdy[hdy_side ? TYB + 1 : 0][hdy_c] = hdy;
         }
         __syncthreads();
-        if (upd_col) {
-            const int p = z * plane + cidx;
-            const C<R> u = q[2];
-            C<R> F;
-            if constexpr (ST == 0) {
-                const C<R> alap = lap3<R>(dx, dy, dz0, sdx[ty][tx], sdx[ty][tx + 2], sdy[ty][tx], sdy[ty + 2][tx],
-                                          dzm, dzp, lc.A76, lc.A112);
-                F = rhs_a<R>(alap, u, ops.vv, s);
-            } else if constexpr (ST == 2) {   // a/h^2 (D^x + D^y + D^z) from the unscaled differences
-                F = rhs_a<R>(cscale<R>((R)(A.c.a * A.c.ih2), cadd<R>(cadd<R>(dx, dy), dz0)), u, ops.vv, s);
-            } else {
-                F = rhs<R>(lapnc, u, ops.vv, (R)A.c.a, s);
-            }
-            if (STAGE == 1) {
-                const C<M> base = in_is_r ? cvt<M, R>(u) : ops.pn;
-                K[p] = F;
-                out[p] = cvt<R, M>(axpy_m<R, M>(base, ck, F));
-            } else if (STAGE <= 3) {
-                K[p] = kacc<R>(ops.kt, F);
-                out[p] = cvt<R, M>(axpy_m<R, M>(ops.pn, ck, F));
-            } else {
-                psin[p] = axpy_m<R, M>(ops.pn, ck, cadd<R>(ops.kt, F));
-            }
-        }
+        // The prefetched plane joins the queues, and its loads are waited for (settle), before
+        // this plane's stores are issued.
+        const C<R> u = q[2], dzm_c = dzm, dz0_c = dz0;
+        const Ops cur = ops;
         q[0] = q[1];
         q[1] = q[2];
         q[2] = q[3];
@@ -235,6 +215,35 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
         ops = nops;
         dzm = dz0;
         dz0 = dzp;
+        settle(q[4]);
+        settle(hx);
+        settle(hy);
+        if constexpr (STAGE >= 2 || !in_is_r) settle(ops.pn);
+        if constexpr (STAGE >= 2) settle(ops.kt);
+        settle(ops.vv);
+        if (upd_col) {
+            const int p = z * plane + cidx;
+            C<R> F;
+            if constexpr (ST == 0) {
+                const C<R> alap = lap3<R>(dx, dy, dz0_c, sdx[ty][tx], sdx[ty][tx + 2], sdy[ty][tx], sdy[ty + 2][tx],
+                                          dzm_c, dzp, lc.A76, lc.A112);
+                F = rhs_a<R>(alap, u, cur.vv, s);
+            } else if constexpr (ST == 2) {   // a/h^2 (D^x + D^y + D^z) from the unscaled differences
+                F = rhs_a<R>(cscale<R>((R)(A.c.a * A.c.ih2), cadd<R>(cadd<R>(dx, dy), dz0_c)), u, cur.vv, s);
+            } else {
+                F = rhs<R>(lapnc, u, cur.vv, (R)A.c.a, s);
+            }
+            if (STAGE == 1) {
+                const C<M> base = in_is_r ? cvt<M, R>(u) : cur.pn;
+                K[p] = F;
+                out[p] = cvt<R, M>(axpy_m<R, M>(base, ck, F));
+            } else if (STAGE <= 3) {
+                K[p] = kacc<R>(cur.kt, F);
+                out[p] = cvt<R, M>(axpy_m<R, M>(cur.pn, ck, F));
+            } else {
+                psin[p] = axpy_m<R, M>(cur.pn, ck, cadd<R>(cur.kt, F));
+            }
+        }
     }
 }
 

@@ -37,6 +37,7 @@ template <typename T, typename U> struct same_p { static constexpr bool v = fals
 template <typename T> struct same_p<T, T> { static constexpr bool v = true; };
 
 constexpr int PW = 64;          // thread-tile width: one wave per row
+
 constexpr int OXW = PW - 4;     // output columns per tile
 
 template <typename IN, typename R, typename M, int TY, int TZ, int PAIR>
@@ -64,6 +65,9 @@ __global__ __launch_bounds__(PW * TY) void pair3d_kernel(Step3DArgs A, int tiles
     const bool col_int = x >= 1 && x < nx && y >= 1 && y < ny;
     const bool col_out = col_int && tx >= 2 && tx < PW - 2 && ty >= 2 && ty < TY - 2;
     const int cidx = col_in ? y * px + x + ox : 0;          // own column, plane 0
+    const int fzi = col_in ? y * (nx + 1) + x : 0;          // own column in the z faces
+    // The tile's threads touch a boundary face (block-uniform): only then do they read face values.
+    const bool tile_face = xs <= 1 || xs + PW >= nx || ys <= 1 || ys + TY >= ny;
 
     const R s = (R)A.c.s;
     const Step2Coef<R> lc = step2_coef<R>(A.c.a, A.c.c76, A.c.c112, A.c.ih2);   // 1/h^2 and a folded in
@@ -115,26 +119,35 @@ __global__ __launch_bounds__(PW * TY) void pair3d_kernel(Step3DArgs A, int tiles
     const bool hdy_in = hdy_role && hdy_col >= 0 && hdy_col <= nx;
     const int hdy_face = hdy_in ? (hdy_row == 0 ? 0 : hdy_row == ny ? 1 : -1) : -1;
 
+    // Loads are unconditional, from a plane clamped into the grid (every idx above is a valid
+    // node of a plane), and the value is then selected: a branch around a load costs scalar
+    // exec-mask work on every plane and waits for every load in flight where it joins.
     auto ldi = [&](int zz, int idx, bool ok) -> C<IN> {   // stage input at plane zz
-        return (ok && zz >= 0 && zz <= nz) ? in[zz * plane + idx] : mk<IN>(IN(0), IN(0));
+        const C<IN> v = in[min(max(zz, 0), nz) * plane + idx];
+        return (ok && zz >= 0 && zz <= nz) ? v : mk<IN>(IN(0), IN(0));
     };
     // D^z from three planes of a column, or the z-face value on a boundary plane
     auto dz_at = [&](int zz, const C<R> &m, const C<R> &c, const C<R> &p) -> C<R> {
-        if (!col_in || zz < 0 || zz > nz) return czero<R>();
-        if (zz == 0) return unscaled<R>(DBz[y * (nx + 1) + x], lc.h2);
-        if (zz == nz) return unscaled<R>(DBz[fz + y * (nx + 1) + x], lc.h2);
-        return d2u<R>(m, c, p);
+        C<R> d = d2u<R>(m, c, p);
+        if (zz == 0 || zz == nz) d = unscaled<R>(DBz[(zz == 0 ? 0 : fz) + fzi], lc.h2);   // block-uniform
+        return (col_in && zz >= 0 && zz <= nz) ? d : czero<R>();
     };
     struct Ops { C<M> pn; C<R> kt; R vv; };   // alpha's update operands at one plane
     auto ld_ops = [&](int zz) -> Ops {
+        const bool ok = col_int && zz >= 1 && zz < nz;
+        const int p = min(max(zz, 1), nz - 1) * plane + cidx;
         Ops o{mk<M>(M(0), M(0)), czero<R>(), R(0)};
-        if (col_int && zz >= 1 && zz < nz) {
-            const int p = zz * plane + cidx;
-            if (PAIR == 2) {
-                o.pn = psin[p];
-                o.kt = Kin[p];
+        if (PAIR == 2) {
+            const C<M> pn = psin[p];
+            const C<R> kt = Kin[p];
+            if (ok) {
+                o.pn = pn;
+                o.kt = kt;
             }
-            if (V) o.vv = V[p];
+        }
+        if (V) {
+            const R vv = V[p];
+            if (ok) o.vv = vv;
         }
         return o;
     };
@@ -188,7 +201,7 @@ __global__ __launch_bounds__(PW * TY) void pair3d_kernel(Step3DArgs A, int tiles
             const C<R> ub = pa[ty][tx];
             bdx = d2u<R>(pa[ty][xl], ub, pa[ty][xr]);   // tile-border threads: unused
             bdy = d2u<R>(pa[yl][tx], ub, pa[yr][tx]);
-            if (col_in) {   // zb lies in 1 .. nz-1
+            if (tile_face && col_in) {   // zb lies in 1 .. nz-1
                 if (x == 0) bdx = unscaled<R>(DBx[zb * (ny + 1) + y], lc.h2);
                 else if (x == nx) bdx = unscaled<R>(DBx[fx + zb * (ny + 1) + y], lc.h2);
                 if (y == 0) bdy = unscaled<R>(DBy[zb * (nx + 1) + x], lc.h2);
@@ -199,7 +212,7 @@ __global__ __launch_bounds__(PW * TY) void pair3d_kernel(Step3DArgs A, int tiles
         }
         C<R> dx = d2u<R>(sp[ty + 2][tx + 1], u, sp[ty + 2][tx + 3]);
         C<R> dy = d2u<R>(sp[ty + 1][tx + 2], u, sp[ty + 3][tx + 2]);
-        if (col_in && zin) {
+        if (tile_face && col_in && zin) {
             if (x == 0) dx = unscaled<R>(DBx[za * (ny + 1) + y], lc.h2);
             else if (x == nx) dx = unscaled<R>(DBx[fx + za * (ny + 1) + y], lc.h2);
             if (y == 0) dy = unscaled<R>(DBy[za * (nx + 1) + x], lc.h2);
@@ -210,27 +223,32 @@ __global__ __launch_bounds__(PW * TY) void pair3d_kernel(Step3DArgs A, int tiles
         if (hdx_role) {
             const int c = hdx_side ? PW + 2 : 1;
             C<R> hdx = d2u<R>(sp[hdx_r + 2][c - 1], sp[hdx_r + 2][c], sp[hdx_r + 2][c + 1]);
-            if (hdx_face >= 0 && zin) hdx = unscaled<R>(DBx[hdx_face * fx + za * (ny + 1) + hdx_row], lc.h2);
+            if (tile_face && hdx_face >= 0 && zin) hdx = unscaled<R>(DBx[hdx_face * fx + za * (ny + 1) + hdx_row], lc.h2);
             sdx[hdx_r][hdx_side ? PW + 1 : 0] = hdx;
         }
         if (hdy_role) {
             const int r = hdy_side ? TY + 2 : 1;
             C<R> hdy = d2u<R>(sp[r - 1][hdy_c + 2], sp[r][hdy_c + 2], sp[r + 1][hdy_c + 2]);
-            if (hdy_face >= 0 && zin) hdy = unscaled<R>(DBy[hdy_face * fy + za * (nx + 1) + hdy_col], lc.h2);
+            if (tile_face && hdy_face >= 0 && zin) hdy = unscaled<R>(DBy[hdy_face * fy + za * (nx + 1) + hdy_col], lc.h2);
             sdy[hdy_side ? TY + 1 : 0][hdy_c] = hdy;
         }
         __syncthreads();
         C<R> ua = u, ka = czero<R>();   // alpha's field (boundary: unchanged) and K after alpha
-        if (col_int && za >= 1 && za < nz) {
+        if (za >= 1 && za < nz) {   // block-uniform; every lane computes, interior lanes keep it
             const C<R> alap = lap3<R>(dx, dy, dza[1], sdx[ty][tx], sdx[ty][tx + 2], sdy[ty][tx], sdy[ty + 2][tx],
                                       dza[0], dza[2], lc.A76, lc.A112);
             const C<R> F = rhs_a<R>(alap, u, ops.vv, s);
+            C<R> kn, un;
             if (PAIR == 1) {   // stage 1: K = F, field Psi^n + (k/2) F
-                ka = F;
-                ua = cvt<R, M>(axpy_m<R, M>(cvt<M, IN>(qi[2]), ck_a, F));
+                kn = F;
+                un = cvt<R, M>(axpy_m<R, M>(cvt<M, IN>(qi[2]), ck_a, F));
             } else {           // stage 3: K += 2F, field Psi^n + k F
-                ka = kacc<R>(ops.kt, F);
-                ua = cvt<R, M>(axpy_m<R, M>(ops.pn, ck_a, F));
+                kn = kacc<R>(ops.kt, F);
+                un = cvt<R, M>(axpy_m<R, M>(ops.pn, ck_a, F));
+            }
+            if (col_int) {
+                ka = kn;
+                ua = un;
             }
         }
 #pragma unroll
@@ -252,6 +270,23 @@ __global__ __launch_bounds__(PW * TY) void pair3d_kernel(Step3DArgs A, int tiles
         dzb[2] = dz_at(za - 1, qa[2], qa[3], qa[4]);
         if (za >= z0 - 2) sa[(za + 3) % 3][ty][tx] = ua;   // for beta two planes on (slot of plane za - 3)
 
+        // The prefetched plane joins the queues, and its loads are waited for (settle), before
+        // beta's stores are issued.
+        const C<IN> q_zb = qi[0];   // Psi^n at zb (pair 1)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) qi[k] = qi[k + 1];
+        qi[4] = qn;
+        hx = nhx;
+        hy = nhy;
+        ops = nops;
+        settle(qi[4]);
+        settle(hx);
+        settle(hy);
+        if constexpr (PAIR == 2) {
+            settle(ops.pn);
+            settle(ops.kt);
+        }
+        settle(ops.vv);
         // ---- beta at plane zb on the inner columns
         if (beta) {
             const C<R> ub = qa[2];
@@ -260,9 +295,9 @@ __global__ __launch_bounds__(PW * TY) void pair3d_kernel(Step3DArgs A, int tiles
                                           sby[ty + 1][tx], dzb[0], dzb[2], lc.A76, lc.A112);
                 const C<R> F = rhs_a<R>(alap, ub, vq[2], s);
                 const int p = zb * plane + cidx;
-                if (PAIR == 1) {   // stage 2: K += 2F, B = Psi^n + (k/2) F (Psi^n at zb is qi[0])
+                if (PAIR == 1) {   // stage 2: K += 2F, B = Psi^n + (k/2) F
                     Kout[p] = kacc<R>(kq[2], F);
-                    Bout[p] = cvt<R, M>(axpy_m<R, M>(cvt<M, IN>(qi[0]), ck_b, F));
+                    Bout[p] = cvt<R, M>(axpy_m<R, M>(cvt<M, IN>(q_zb), ck_b, F));
                 } else {           // stage 4: Psi^{n+1} = Psi^n + (k/6)(K + F)
                     pout[p] = axpy_m<R, M>(pq[2], ck_b, cadd<R>(kq[2], F));
                 }
@@ -271,12 +306,6 @@ __global__ __launch_bounds__(PW * TY) void pair3d_kernel(Step3DArgs A, int tiles
         // The next plane writes sp before its first barrier (every read of sp came before this
         // plane's second barrier) and sdx, sdy, sbx, sby only after it; alpha's field goes to
         // slot za mod 3 after the second barrier, while beta read slot zb mod 3 before it.
-#pragma unroll
-        for (int k = 0; k < 4; ++k) qi[k] = qi[k + 1];
-        qi[4] = qn;
-        hx = nhx;
-        hy = nhy;
-        ops = nops;
     }
 }
 
