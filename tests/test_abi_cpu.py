@@ -80,6 +80,13 @@ def test_parameter_validation_before_any_allocation():
             assert e.code == -1, (e.code, e)
         else:
             raise AssertionError("invalid parameters accepted")
+    for prec, n in (("f64", 5120), ("f32", 9216), ("mixed", 9216)):   # one node beyond the 1D on-chip limit
+        try:
+            P.Solver(1, n, 0.01, 1.0, 1.0, stream=None, prec=prec)
+        except P.NLSEError as e:
+            assert e.code == -6, (prec, n, e.code, e)
+        else:
+            raise AssertionError("1D field beyond the on-chip solver accepted")
     for args, code in (((3, 1300, 0.1, 1.0, 1.0), -6),             # 3D beyond 32-bit offsets
                        ((3, (2000, 1000, 1200), 0.1, 1.0, 1.0), -6),
                        ((2, 10 ** 9, 0.1, 1.0, 1.0), -4)):          # no device holds it

@@ -171,15 +171,18 @@ def test_1d_msd_dark_soliton(gpu, orc, prec):
     assert rel(g, ref) <= TOL[prec]
 
 
-@pytest.mark.parametrize("n", [2, 3, 1023, 5119])
-def test_1d_sizes(gpu, orc, n):
+@pytest.mark.parametrize("n,prec", [(2, "f64"), (3, "f64"), (1023, "f64"), (5119, "f64"), (2, "f32"),
+                                    (9215, "f32"), (9215, "mixed")])
+def test_1d_sizes(gpu, orc, n, prec):
+    """From the smallest grid to the largest the on-chip solver holds (5120 nodes in FP64, 9216 in
+    FP32 and mixed precision)."""
     g = I.grid(1, n, -10, 10)
     (x,) = g.coords()
     psi = I.bright_soliton(x, 0.0, 1.0, 1.0, 1.2, 0.3)
     psi[0] = psi[-1] = 0
     sp = I.ProblemSpec("sizes1d", g, 1.0, 1.0, 0.05 * x * x, psi, "dirichlet")
-    gg, ref, s, P = run_both(gpu, orc, sp, "f64", 40)
-    assert rel(gg, ref) <= 1e-12
+    gg, ref, s, P = run_both(gpu, orc, sp, prec, 40)
+    assert rel(gg, ref) <= TOL[prec]
 
 
 # ------------------------------------------------------------------- 3D --
