@@ -6,13 +6,15 @@
 //   K     K_tot                   (stage precision)
 //   V     potential               (real, stage precision; absent when V = 0)
 //   DB    boundary-face closure values of the per-axis 2SHOC (2D / 3D)
-//   psi2  2D only: a second master buffer for the whole-step kernel
+//   psi2  2D, and 3D under Dirichlet: a second master buffer for the 2D whole-step
+//         and 3D two-stage kernels
 // With the stage-kernel variants one RK4 step enqueues four fused stage kernels:
 //   S1 psi -> A, S2 A -> B, S3 B -> A, S4 A -> psi
-// The ping-pong keeps every stage's stencil input read-only while the next stage
-// field is written.  The 2D whole-step variants enqueue one kernel per step,
-// psi -> psi2, and then swap the two pointers.  1D contexts run all steps in
-// one persistent launch.
+// (under MSD each preceded by the boundary launch of msd.hip).  The ping-pong keeps
+// every stage's stencil input read-only while the next stage field is written.
+// The 2D whole-step variants enqueue one kernel per step, psi -> psi2; the 3D
+// two-stage variants two, psi -> K, B and B, K, psi -> psi2; both then swap the
+// two master pointers.  1D contexts run all steps in one persistent launch.
 #include <cmath>
 #include <cstdio>
 #include <cstring>

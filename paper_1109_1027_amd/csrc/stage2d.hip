@@ -15,8 +15,8 @@
 // face values the per-axis and single-storage forms (Eq. 2d2shocs1-2) are
 // algebraically identical.  Under Dirichlet the boundary values never change, so
 // D^a_b are constants computed once per field (launch_boundary_d); under MSD
-// msd.hip forms them from the stage's input before each launch and updates the
-// boundary nodes after it.  Either way only boundary tiles read them.
+// msd.hip forms them from the stage's input, and updates the boundary nodes, in a
+// launch before each stage launch.  Either way only boundary tiles read them.
 //
 // Tiling.  A wave owns 64 consecutive interior columns (aligned, one row segment
 // = one coalesced access) and RW rows (RW = 4, 8 or 16: the tile variants the
