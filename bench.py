@@ -248,6 +248,7 @@ def bench_1d(P, I):
     for prec in ("f64", "f32"):
         s = P.Solver.from_spec(sp, prec=prec)
         s.set_field(sp.psi0)
+        variant = s.autotune(reps=8)   # workgroup size of the on-chip solver (untimed)
         nsteps = int(math.ceil(sp.t_end / (0.5 * s.max_dt())))
         dt = sp.t_end / nsteps
         s.step(10, dt)   # warm-up (discarded)
@@ -263,7 +264,7 @@ def bench_1d(P, I):
         s.close()
         err = float(np.linalg.norm(g - exact) / np.linalg.norm(exact))
         res[prec] = {"steps": nsteps, "run_ms": ms, "us_per_step": 1e3 * ms / nsteps, "rel_l2_vs_exact": err,
-                     "launches": 1}
+                     "launches": 1, "solver_variant": variant}
         print(f"[bench] 1D soliton {prec}: {nsteps} steps in {ms:.2f} ms ({1e3 * ms / nsteps:.2f} us/step), "
               f"rel L2 vs exact {err:.3e}", file=sys.stderr, flush=True)
     return res

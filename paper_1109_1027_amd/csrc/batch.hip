@@ -132,7 +132,20 @@ __global__ __launch_bounds__(BS) void batch1d_kernel(const BatchItem *items, con
         a.k6 = I.dt / 6.0;
         a.nsteps = nsteps;
         a.msd = I.msd;
-        solve1d_onchip<R, M, BS, NPT>(a, smem);
+        // The solver body with the smallest node bound that holds the instance: every slot
+        // of its register arrays costs instructions whether used or not.
+        const int npt = max(3, (int)((I.L.nx + 1 + BS - 1) / BS));
+        if (npt <= 3) {
+            solve1d_onchip<R, M, BS, 3>(a, smem);
+        } else if (npt <= 5) {
+            if constexpr (NPT > 5) solve1d_onchip<R, M, BS, 5>(a, smem);
+            else solve1d_onchip<R, M, BS, NPT>(a, smem);
+        } else if (npt <= 7) {
+            if constexpr (NPT > 7) solve1d_onchip<R, M, BS, 7>(a, smem);
+            else solve1d_onchip<R, M, BS, NPT>(a, smem);
+        } else {
+            solve1d_onchip<R, M, BS, NPT>(a, smem);
+        }
     }
 }
 

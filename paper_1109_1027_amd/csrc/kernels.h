@@ -81,9 +81,11 @@ struct Solve1DArgs {
     double k, k2, k6;
     int64_t nsteps;
     int msd;             // 1: MSD boundary, 0: Dirichlet
+    int variant;         // 0: 512 threads, 1: 256 threads, 2 / 3: 512 threads with at most 4 / 3 nodes each
 };
 hipError_t launch_solve1d(Prec prec, const Solve1DArgs &a, hipStream_t st);
-int64_t solve1d_max_nodes(Prec prec);
+int64_t solve1d_max_nodes(Prec prec);               // the largest field of variant 0
+int solve1d_variants(Prec prec, int64_t nodes);     // variants 0 .. that hold `nodes`
 
 // Boundary-face normal second differences D^a_b = Lap_b - sum_{tangential} delta^2 Psi_b
 // for the per-axis 2SHOC (Dirichlet, 2D/3D), from the master field.

@@ -135,7 +135,7 @@ static int variant_count(const nlse_ctx *c)
 {
     if (c->p.ndim == 2) return stage2d_variants() + (step2d_ok(c) ? step2d_variants() : 0);
     if (c->p.ndim == 3) return stage3d_variants() + (step3d_ok(c) ? step3d_variants() : 0);
-    return 1;
+    return solve1d_variants(c->prec, c->L.nx + 1);
 }
 
 // Variants that write Psi^{n+1} into the second master buffer (2D whole step, 3D pairs).
@@ -188,8 +188,26 @@ static hipError_t launch_whole_step(nlse_ctx *c, double dt, int variant)
 }
 
 // One RK4 step with the given variant.
+// A 1D context: `nsteps` RK4 steps in one launch of the on-chip solver.
+static hipError_t launch_1d(nlse_ctx *c, double dt, int64_t nsteps, int variant)
+{
+    Solve1DArgs a;
+    a.psin = c->psi;
+    a.V = c->V;
+    a.L = c->L;
+    a.c = base_coeffs(c->p);
+    a.k = dt;
+    a.k2 = dt / 2.0;
+    a.k6 = dt / 6.0;
+    a.nsteps = nsteps;
+    a.msd = c->p.bc == NLSE_BC_MSD;
+    a.variant = variant;
+    return launch_solve1d(c->prec, a, c->stream);
+}
+
 static hipError_t launch_rk4_step(nlse_ctx *c, double dt, int variant)
 {
+    if (c->p.ndim == 1) return launch_1d(c, dt, 1, variant);
     if (whole_step(c, variant)) return c->p.ndim == 2 ? launch_whole_step(c, dt, variant) : launch_pair_step(c, dt, variant);
     for (int st = 1; st <= 4; ++st) {
         hipError_t e = launch_stage(c, st, dt, variant);
@@ -276,7 +294,8 @@ int nlse_autotune(nlse_ctx *c, int reps, int force, int *chosen)
             for (int v = 0; v < nv && e == hipSuccess; ++v) {
                 e = launch_rk4_step(c, dt, v);   // warm
                 if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-                for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_rk4_step(c, dt, v);
+                if (c->p.ndim == 1 && e == hipSuccess) e = launch_1d(c, dt, 16 * (int64_t)reps, v);   // one launch
+                for (int r = 0; r < reps && c->p.ndim > 1 && e == hipSuccess; ++r) e = launch_rk4_step(c, dt, v);
                 if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float ms = 0.f;
@@ -552,19 +571,8 @@ int nlse_step(nlse_ctx *c, int64_t nsteps, double dt)
         return fail(NLSE_E_DT_UNSTABLE, buf);
     }
     if (nsteps == 0) return NLSE_OK;
-    Coeffs co = base_coeffs(c->p);
     if (c->p.ndim == 1) {
-        Solve1DArgs a;
-        a.psin = c->psi;
-        a.V = c->V;
-        a.L = c->L;
-        a.c = co;
-        a.k = dt;
-        a.k2 = dt / 2.0;
-        a.k6 = dt / 6.0;
-        a.nsteps = nsteps;
-        a.msd = c->p.bc == NLSE_BC_MSD;
-        HIPTRY(launch_solve1d(c->prec, a, c->stream));
+        HIPTRY(launch_1d(c, dt, nsteps, c->variant));
         return NLSE_OK;
     }
     for (int64_t step = 0; step < nsteps; ++step) {

@@ -372,6 +372,57 @@ def test_variants_bitwise_identical(gpu, dim):
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+@pytest.mark.parametrize("n,bc", [(1024, "dirichlet"), (1500, "msd"), (8, "msd"), (2, "dirichlet"), (4095, "dirichlet")])
+def test_1d_variants_bitwise_identical(gpu, orc, prec, n, bc):
+    """The 1D solver's variants (512 or 256 threads, at most 10 / 18, 4 or 3 nodes per thread) partition
+    the nodes differently and must give the same bits; a variant is offered only while it holds the field.
+    (Tiny MSD grids are kept at h = 1: with n = 4 or 6 the moving notch reaches b-1 within a few
+    steps and the MSD ratio F_{b-1}/Psi_{b-1} blows up, in the oracle as on the GPU.)"""
+    half = 20.0 if n >= 100 else n / 2.0
+    g = I.grid(1, n, -half, half)
+    (x,) = g.coords()
+    if bc == "msd":
+        psi = I.dark_soliton(x, 0.0, a=1.0, s=-1.0, omega=-1.0, c=0.5)
+    else:
+        psi = I.bright_soliton(x, 0.0, 1.0, 1.0, 1.0, 0.5)
+        psi[0] = psi[-1] = 0
+    sp = I.ProblemSpec("v1d", g, 1.0, -1.0 if bc == "msd" else 1.0, 0.01 * x * x, psi.astype(np.complex128), bc)
+    npt = 10 if prec == "f64" else 18
+    caps = (512 * npt, 256 * npt, 512 * 4, 512 * 3)
+    expect = next((i for i, c in enumerate(caps) if c < n + 1), 4)
+    outs = []
+    for v in range(expect):
+        s = gpu.Solver.from_spec(sp, prec=prec)
+        assert s.variant_count() == expect
+        s.set_field(sp.psi0)
+        s.variant = v
+        say(f"[case] 1D {bc} n={n} {prec} variant {v}")
+        s.step(25, 0.5 * s.max_dt())
+        outs.append(s.get_field())
+        s.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    P = orc.Problem.from_spec(sp)
+    ref = P.rk4(sp.psi0, 25, 0.5 * P.max_dt(sp.psi0))
+    assert rel(outs[0], ref) <= TOL[prec]
+
+
+def test_1d_autotune_keeps_state(gpu):
+    sp = I.config_soliton_1d(1024)
+    a = gpu.Solver.from_spec(sp)
+    a.set_field(sp.psi0)
+    dt = 0.5 * a.max_dt()
+    a.step(5, dt)
+    v = a.autotune(reps=4, force=True)
+    assert 0 <= v < a.variant_count() == 4
+    a.step(5, dt)
+    b = gpu.Solver.from_spec(sp)
+    b.set_field(sp.psi0)
+    b.step(10, dt)
+    assert np.array_equal(a.get_field(), b.get_field())
+
+
 def test_autotune_keeps_state(gpu):
     sp = I.config_gp2d(n=200)
     a = gpu.Solver.from_spec(sp)
