@@ -158,8 +158,11 @@ int nlse_launches_per_step(const nlse_ctx *c);
  * 3D: 0-3 stage kernels with 64 x 4 or 64 x 8 column tiles marching 16, 32 or 64 planes;
  * 4-6 (Dirichlet, fields below 2^31 elements) two launches per step, each fusing two stages
  * (1+2, 3+4) on 64 x 16 or 64 x 8 column tiles marching 32 or 64 planes.
- * Every variant computes bit-identical fields; they differ only in speed.  1D contexts
- * have one. */
+ * 1D: the on-chip solver with 512 threads holding up to 10 (FP64) or 18 (FP32, mixed)
+ * nodes each (0), 256 threads with as many (1), 512 threads with at most 4 (2) or 3 (3)
+ * nodes each; a variant is offered only while it holds the field (5120 / 9216, 2560 /
+ * 4608, 2048 and 1536 nodes), so the count is 1 to 4.
+ * Every variant computes bit-identical fields; they differ only in speed. */
 int nlse_variant_count(const nlse_ctx *c);
 int nlse_set_variant(nlse_ctx *c, int variant);   /* NLSE_E_INVAL if out of range */
 int nlse_get_variant(const nlse_ctx *c);
@@ -210,8 +213,10 @@ int nlse_batch_mass(nlse_batch *b, int32_t i, double *out);
  * stream (asynchronous).  NLSE_E_INVAL if an instance lacks a field or a dt. */
 int nlse_batch_step(nlse_batch *b, int64_t nsteps);
 int nlse_batch_sync(nlse_batch *b);
-/* Tile variants of the 2D instances (rows per wave: 8 or 4 in FP32 / mixed, 4 or 2
- * in FP64) and the autotuner that times nsteps of each, restoring the state. */
+/* Variants of the 2D instances (row segments of 56, 29 or 20 rows for the whole-step wave
+ * body) and the autotuner that times nsteps of each, restoring the state.  A 1D instance
+ * always runs the on-chip solver body with the smallest node bound per thread that holds
+ * it. */
 int nlse_batch_variant_count(const nlse_batch *b);
 int nlse_batch_set_variant(nlse_batch *b, int variant);
 int nlse_batch_get_variant(const nlse_batch *b);
