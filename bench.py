@@ -246,27 +246,33 @@ def bench_1d(P, I):
     exact = I.bright_soliton(x, sp.t_end, 1.0, 1.0, 1.0, 0.5)
     res = {"workload": "1D bright soliton, 1025 nodes, a = s = 1, t = 10, dt = 0.5 k_max (config 1)"}
     for prec in ("f64", "f32"):
-        s = P.Solver.from_spec(sp, prec=prec)
-        s.set_field(sp.psi0)
-        variant = s.autotune(reps=8)   # workgroup size of the on-chip solver (untimed)
-        nsteps = int(math.ceil(sp.t_end / (0.5 * s.max_dt())))
-        dt = sp.t_end / nsteps
-        s.step(10, dt)   # warm-up (discarded)
-        s.set_field(sp.psi0)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(torch.cuda.current_stream())
-        s.step(nsteps, dt)
-        e1.record(torch.cuda.current_stream())
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        g = np.asarray(s.get_field(), np.complex128)
-        s.close()
-        err = float(np.linalg.norm(g - exact) / np.linalg.norm(exact))
-        res[prec] = {"steps": nsteps, "run_ms": ms, "us_per_step": 1e3 * ms / nsteps, "rel_l2_vs_exact": err,
-                     "launches": 1, "solver_variant": variant}
-        print(f"[bench] 1D soliton {prec}: {nsteps} steps in {ms:.2f} ms ({1e3 * ms / nsteps:.2f} us/step), "
-              f"rel L2 vs exact {err:.3e}", file=sys.stderr, flush=True)
+        for st in ("2shoc", "noncompact", "cd"):   # Sec. 5's comparison in 1D (on chip: latency, not bytes)
+            s = P.Solver.from_spec(sp, prec=prec)
+            s.stencil = st
+            s.set_field(sp.psi0)
+            variant = s.autotune(reps=8)   # workgroup size / node bound of the on-chip solver (untimed)
+            nsteps = int(math.ceil(sp.t_end / (0.5 * s.max_dt())))
+            dt = sp.t_end / nsteps
+            s.step(10, dt)   # warm-up (discarded)
+            s.set_field(sp.psi0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(torch.cuda.current_stream())
+            s.step(nsteps, dt)
+            e1.record(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            g = np.asarray(s.get_field(), np.complex128)
+            s.close()
+            err = float(np.linalg.norm(g - exact) / np.linalg.norm(exact))
+            r = {"steps": nsteps, "run_ms": ms, "us_per_step": 1e3 * ms / nsteps, "rel_l2_vs_exact": err,
+                 "launches": 1, "solver_variant": variant}
+            if st == "2shoc":
+                res[prec] = r
+            else:
+                res[prec].setdefault("stencils", {})[st] = r
+            print(f"[bench] 1D soliton {prec} {st}: {nsteps} steps in {ms:.2f} ms ({1e3 * ms / nsteps:.2f} us/step), "
+                  f"rel L2 vs exact {err:.3e}", file=sys.stderr, flush=True)
     return res
 
 

@@ -167,12 +167,13 @@ int nlse_variant_count(const nlse_ctx *c);
 int nlse_set_variant(nlse_ctx *c, int variant);   /* NLSE_E_INVAL if out of range */
 int nlse_get_variant(const nlse_ctx *c);
 
-/* Laplacian of the right-hand side (2D and 3D contexts with Dirichlet boundaries;
- * NLSE_E_UNSUPPORTED for the alternatives in 1D or under MSD, NLSE_E_INVAL for an
- * unknown value).  In 3D the non-compact stencil is the 13-point cross, one five-point
- * difference per axis (Sec. 2.3).  The alternatives run in the stage kernels only, so
- * the 2D whole-step and 3D two-stage variants disappear from the variant list while
- * they are selected (such a variant then reverts to variant 0).
+/* Laplacian of the right-hand side (Dirichlet boundaries; NLSE_E_UNSUPPORTED for the
+ * alternatives under MSD, NLSE_E_INVAL for an unknown value).  The non-compact stencil
+ * is one five-point difference per axis: the 1D stencil of Sec. 2.1, the 9-point cross of
+ * Eq. 2dnonhoc in 2D, the 13-point cross in 3D (Sec. 2.3).  In 2D and 3D the
+ * alternatives run in the stage kernels only, so the whole-step and two-stage variants
+ * disappear from the variant list while they are selected (such a variant then reverts
+ * to variant 0); the 1D on-chip solver runs them in every variant.
  * nlse_max_dt keeps the 2SHOC bound of Eq. kdfull (the non-compact stencil has the
  * same spectral radius, CD a smaller one), and nlse_energy always uses the 2SHOC
  * Laplacian.  For the comparisons of Sec. 5 on this hardware. */

@@ -132,6 +132,8 @@ __global__ __launch_bounds__(BS) void batch1d_kernel(const BatchItem *items, con
         a.k6 = I.dt / 6.0;
         a.nsteps = nsteps;
         a.msd = I.msd;
+        a.variant = 0;
+        a.stencil = 0;
         // The solver body with the smallest node bound that holds the instance: every slot
         // of its register arrays costs instructions whether used or not.
         const int npt = max(3, (int)((I.L.nx + 1 + BS - 1) / BS));

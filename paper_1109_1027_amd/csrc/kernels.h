@@ -25,7 +25,7 @@ struct StageArgs {
     Coeffs c;
     int stage;
     int variant;        // tile-shape variant (see stage2d_variants / stage3d_variants)
-    int stencil;        // 0 2SHOC, 1 non-compact fourth order, 2 second-order CD (2D/3D)
+    int stencil;        // 0 2SHOC, 1 non-compact fourth order, 2 second-order CD
 };
 
 // 2D fused stage kernel: per-axis 2SHOC, one 64-column x RW-row tile per wave.
@@ -82,6 +82,7 @@ struct Solve1DArgs {
     int64_t nsteps;
     int msd;             // 1: MSD boundary, 0: Dirichlet
     int variant;         // 0: 512 threads, 1: 256 threads, 2 / 3: 512 threads with at most 4 / 3 nodes each
+    int stencil;         // 0 2SHOC, 1 non-compact fourth order, 2 second-order CD (Dirichlet only)
 };
 hipError_t launch_solve1d(Prec prec, const Solve1DArgs &a, hipStream_t st);
 int64_t solve1d_max_nodes(Prec prec);               // the largest field of variant 0

@@ -202,6 +202,7 @@ static hipError_t launch_1d(nlse_ctx *c, double dt, int64_t nsteps, int variant)
     a.nsteps = nsteps;
     a.msd = c->p.bc == NLSE_BC_MSD;
     a.variant = variant;
+    a.stencil = c->stencil;
     return launch_solve1d(c->prec, a, c->stream);
 }
 
@@ -244,8 +245,6 @@ int nlse_set_stencil(nlse_ctx *c, int32_t stencil)
 {
     if (!c) return fail(NLSE_E_INVAL, "NULL context");
     if (stencil < NLSE_STENCIL_2SHOC || stencil > NLSE_STENCIL_CD) return fail(NLSE_E_INVAL, "unknown stencil");
-    if (stencil != NLSE_STENCIL_2SHOC && c->p.ndim == 1)
-        return fail(NLSE_E_UNSUPPORTED, "the alternative stencils are implemented in 2D and 3D only");
     if (stencil != NLSE_STENCIL_2SHOC && c->p.bc != NLSE_BC_DIRICHLET)
         return fail(NLSE_E_UNSUPPORTED, "the alternative stencils are implemented for Dirichlet boundaries only");
     c->stencil = stencil;

@@ -12,11 +12,11 @@ template <typename R> struct NPT1D;
 template <> struct NPT1D<double> { static constexpr int v = 10; };   // nodes per thread at most
 template <> struct NPT1D<float> { static constexpr int v = 18; };
 
-template <typename R, typename M, int BS, int NPT>
+template <typename R, typename M, int BS, int NPT, int ST>
 __global__ __launch_bounds__(BS) void solve1d_kernel(Solve1DArgs A)
 {
     extern __shared__ unsigned char smem_raw[];
-    solve1d_onchip<R, M, BS, NPT>(A, smem_raw);
+    solve1d_onchip<R, M, BS, NPT, ST>(A, smem_raw);
 }
 
 static int npt_of(Prec prec) { return prec == P_F64 ? NPT1D<double>::v : NPT1D<float>::v; }
@@ -46,7 +46,12 @@ template <typename R, typename M, int BS, int NPT>
 static hipError_t launch1d(const Solve1DArgs &a, hipStream_t st)
 {
     const size_t lds = onchip1d_lds<R, BS>();
-    hipLaunchKernelGGL((solve1d_kernel<R, M, BS, NPT>), dim3(1), dim3(BS), lds, st, a);
+    switch (a.stencil) {
+    case 0: hipLaunchKernelGGL((solve1d_kernel<R, M, BS, NPT, 0>), dim3(1), dim3(BS), lds, st, a); break;
+    case 1: hipLaunchKernelGGL((solve1d_kernel<R, M, BS, NPT, 1>), dim3(1), dim3(BS), lds, st, a); break;
+    case 2: hipLaunchKernelGGL((solve1d_kernel<R, M, BS, NPT, 2>), dim3(1), dim3(BS), lds, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -65,6 +70,7 @@ static hipError_t launch1d_v(const Solve1DArgs &a, hipStream_t st)
 hipError_t launch_solve1d(Prec prec, const Solve1DArgs &a, hipStream_t st)
 {
     if (a.variant < 0 || a.variant >= solve1d_variants(prec, a.L.nx + 1)) return hipErrorInvalidValue;
+    if (a.stencil != 0 && a.msd) return hipErrorInvalidValue;   // the MSD closure is the 2SHOC one
     switch (prec) {
     case P_F64: return launch1d_v<double, double>(a, st);
     case P_F32: return launch1d_v<float, float>(a, st);

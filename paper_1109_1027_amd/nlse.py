@@ -247,7 +247,7 @@ class Solver:
     def variant(self, v):
         _check(load().nlse_set_variant(self._h, int(v)))
 
-    # ---- Laplacian (2D and 3D stage kernels, Dirichlet): "2shoc" (default), "noncompact", "cd"
+    # ---- Laplacian (Dirichlet; 2D and 3D in the stage kernels): "2shoc" (default), "noncompact", "cd"
     STENCILS = {"2shoc": 0, "noncompact": 1, "cd": 2}
 
     @property

@@ -1,4 +1,4 @@
-"""The alternative 2D and 3D Laplacians of the stage kernels (nlse_set_stencil) against the oracle.
+"""The alternative 1D, 2D and 3D Laplacians (nlse_set_stencil) against the oracle.
 
 The non-compact fourth-order stencil and the second-order CD are what 2SHOC is compared with
 (Sec. 2.1, Sec. 5).  The oracle implements both (lap="noncompact" with odd-reflection ghosts
@@ -140,14 +140,46 @@ def test_stencil3d_variants_bitwise_and_api(gpu, stencil, prec):
         assert np.array_equal(o, outs[0])
 
 
-def test_stencil_unsupported_in_1d_and_under_msd(gpu):
-    sp1 = I.config_soliton_1d(256)
-    s = gpu.Solver.from_spec(sp1)
-    with pytest.raises(gpu.NLSEError):
-        s.stencil = "cd"
-    assert s.stencil == "2shoc"
-    s.close()
-    for dim in (2, 3):
+@pytest.mark.parametrize("stencil", ["noncompact", "cd"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+@pytest.mark.parametrize("n", [2, 3, 5, 1024, 5119])
+def test_stencil1d_parity_with_oracle(gpu, orc, stencil, prec, n):
+    """The on-chip 1D solver with the five-point non-compact stencil (two nodes of each
+    neighbouring thread, odd-reflection ghosts) and with CD, random Dirichlet values; every
+    variant that holds the field gives the same bits."""
+    if prec == "f64" and n + 1 > 5120:
+        pytest.skip("beyond the FP64 on-chip capacity")
+    rng = np.random.default_rng(n)
+    g = I.grid(1, n, -10, 10)
+    (x,) = g.coords()
+    psi = I.bright_soliton(x, 0.0, 1.0, 1.0, 1.2, 0.3).astype(np.complex128)
+    psi[0], psi[-1] = 0.3 * (rng.standard_normal(2) + 1j * rng.standard_normal(2))
+    V = 0.05 * x * x
+    sp = I.ProblemSpec("st1d", g, 1.0, 1.0, V, psi, "dirichlet")
+    dt = 0.5 * orc.Problem.from_spec(sp).max_dt(psi)
+    ref = orc.Problem.from_spec(sp, lap=stencil).rk4(psi, 30, dt)
+    outs = []
+    s0 = gpu.Solver.from_spec(sp, prec=prec)
+    nv = s0.variant_count()
+    s0.close()
+    for v in range(nv):
+        s = gpu.Solver.from_spec(sp, prec=prec)
+        s.stencil = stencil
+        s.variant = v
+        s.set_field(psi.astype(s.dtype))
+        say(f"[case] 1D {stencil} {prec} n={n} variant {v}")
+        s.step(30, dt)
+        outs.append(s.get_field())
+        s.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    e = rel(outs[0], ref)
+    say(f"[result] 1D {stencil} {prec} n={n}: rel L2 {e:.3e}")
+    assert e <= TOL[prec]
+
+
+def test_stencil_unsupported_under_msd(gpu):
+    for dim in (1, 2, 3):
         g = I.grid(dim, 20, -8.0, 8.0)
         s = gpu.Solver(dim, 20, g.h, 0.5, -1.0, None, "msd", "f32")
         for name in ("noncompact", "cd"):
