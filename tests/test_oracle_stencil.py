@@ -166,7 +166,7 @@ def test_cd_is_second_difference(orc):
     np.testing.assert_allclose(out[1:-1, 1:-1], ref, rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("dim,n", [(2, 9), (3, 7)])
+@pytest.mark.parametrize("dim,n", [(1, 12), (2, 9), (3, 7)])
 def test_cd_quartic_closed_form(orc, dim, n):
     """The second difference of x^4 is 12 x^2 + 2 h^2 exactly, so CD(sum_a x_a^4) =
     12 |r|^2 + 2 d h^2 at every interior node (catches a dropped axis or a wrong scale)."""
@@ -178,7 +178,7 @@ def test_cd_quartic_closed_form(orc, dim, n):
     np.testing.assert_allclose(inner(out, dim, 1), inner(ref, dim, 1), rtol=1e-12, atol=1e-12)
 
 
-@pytest.mark.parametrize("dim,n", [(2, 8), (3, 6)])
+@pytest.mark.parametrize("dim,n", [(1, 9), (2, 8), (3, 6)])
 def test_noncompact_odd_ghost_closed_form(orc, dim, n):
     """Odd reflection ghosts with non-zero boundary values.  With x_a measured from the lower
     boundary, the ghost of x^2 is 2 f(0) - f(h) = -h^2 below and the true value - 2 h^2
