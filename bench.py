@@ -376,7 +376,7 @@ def bench_batch(P, I, steps=1000):
 
 def bench_msd(P, I, args, res, npts):
     """2D MSD boundary (Sec. 3.2, extended to 2D): vortex-antivortex pairs in a uniform background,
-    V = 0, on the 2049^2 grid; stage kernels plus the two boundary launches per stage, against the
+    V = 0, on the 2049^2 grid; stage kernels plus the boundary launch before each stage, against the
     Dirichlet stage kernels of the same tile variant."""
     g = I.grid(2, args.n, -80.0, 80.0)
     spec = I.ProblemSpec("msd2d", g, 0.5, -1.0, None, I.background_vortices(g, pairs=4, seed=3), "msd")
@@ -395,6 +395,32 @@ def bench_msd(P, I, args, res, npts):
                      "launches_per_step": launches // steps, "tile_variant": sv,
                      "dirichlet_stage_ms_per_step": ref, "boundary_overhead": ms / steps / ref - 1.0}
         print(f"[bench] MSD 2D {prec} (stage kernels + boundary launches): {gpts:.2f} Gpt*steps/s, "
+              f"{100 * out[prec]['boundary_overhead']:.1f}% over Dirichlet", file=sys.stderr, flush=True)
+    return out
+
+
+def bench_msd3d(P, I, args, res3d):
+    """3D MSD boundary: a vortex ring of radius 8 in a uniform background, V = 0, on the 513^3 grid
+    of config 3 ([-24, 24]^3); stage kernels plus the boundary launch before each stage (1.6 M
+    boundary nodes), against the Dirichlet stage kernels of config 3 with the same tile variant."""
+    g = I.grid(3, args.n3d, -24.0, 24.0)
+    spec = I.ProblemSpec("msd3d", g, 0.5, -1.0, None, I.background_ring(g, ring_radius=8.0), "msd")
+    npts = spec.interior_points
+    out = {"workload": f"3D NLSE with the MSD boundary, {args.n3d + 1}^3 nodes, a=0.5 s=-1 V=0 on [-24,24]^3, "
+                       "a vortex ring of radius 8 in a uniform background", "interior_points": npts}
+    steps = max(args.steps3d // 4, 1)
+    for prec in ("f32",):
+        r = res3d.get(prec, {})
+        if "stage_kernels" not in r:
+            continue
+        sv = r["stage_kernels"]["tile_variant"]
+        ms, _, launches, dt, _, _ = time_solver(P, spec, prec, steps, 3, variant=sv)
+        gpts = npts * steps / (ms * 1e-3) / 1e9
+        ref = r["stage_kernels"]["ms_per_step"]
+        out[prec] = {"value": gpts, "unit": "Gpt·steps/s", "ms_per_step": ms / steps, "dt": dt,
+                     "launches_per_step": launches // steps, "tile_variant": sv,
+                     "dirichlet_stage_ms_per_step": ref, "boundary_overhead": ms / steps / ref - 1.0}
+        print(f"[bench] MSD 3D {prec} (stage kernels + boundary launches): {gpts:.2f} Gpt*steps/s, "
               f"{100 * out[prec]['boundary_overhead']:.1f}% over Dirichlet", file=sys.stderr, flush=True)
     return out
 
@@ -553,6 +579,8 @@ def main():
     out["soliton1d"] = bench_1d(P, I)
     if args.n3d > 0:
         out["gp3d"] = bench_3d(P, I, args)
+        if not args.no_msd and not args.no_stage3d:
+            out["msd3d"] = bench_msd3d(P, I, args, out["gp3d"])
     if args.batch_steps > 0:
         out["batch"] = bench_batch(P, I, args.batch_steps)
     if not args.no_learned:
