@@ -160,6 +160,22 @@ struct DirectFaces {
     __device__ __forceinline__ C<R> operator()(int a, const Node &r) const { return face_closure<IN, R>(f, cf, a, r); }
 };
 
+// ... or, for the thread that has just formed the value at its own face node b, that value
+// there and formed on the spot elsewhere.
+template <typename IN, typename R>
+struct KnownFace {
+    DirectFaces<IN, R> direct;
+    int a;
+    Node b;
+    C<R> value;
+    bool known;
+    __device__ __forceinline__ C<R> operator()(int ax, const Node &r) const
+    {
+        if (known && ax == a && r.x == b.x && r.y == b.y && r.z == b.z) return value;
+        return direct(ax, r);
+    }
+};
+
 // F at the interior node q, per-axis 2SHOC (Eqs. 2d2shocMs1-2, 3d2shocMs1-2) with the face
 // values where q's neighbour along an axis is a boundary node.
 template <typename IN, typename R, typename Faces>
@@ -253,10 +269,13 @@ __global__ void msd_stage_kernel(Field<IN, R> f, StageArgs A, C<R> *DBx, C<R> *D
 #pragma unroll
     for (int t = 0; t < 3; ++t)
         if (t != a && on_bnd(L, b, t)) face = false;
-    const DirectFaces<IN, R> faces{f, A.c};
+    const DirectFaces<IN, R> direct{f, A.c};
+    KnownFace<IN, R> faces{direct, a, b, czero<R>(), false};
     if (face) {
+        faces.value = direct(a, b);
+        faces.known = true;
         C<R> *dst = a == 0 ? DBx : a == 1 ? DBy : DBz;
-        dst[side * face_size(L, a) + fi] = faces(a, b);
+        dst[side * face_size(L, a) + fi] = faces.value;
     }
     if (!owner(L, b, a)) return;
     const Node q = inner(L, b);
