@@ -87,20 +87,24 @@ def parse_variants(spec):
     return out
 
 
-def time_solver(P, spec, prec, steps, warmup, variant=None, stencil=None):
+def time_solver(P, spec, prec, steps, warmup, variant=None, stencil=None, dt=None, check=None):
     """Time `steps` RK4 steps after `warmup` untimed ones; HIP events on the solver's stream.
-    variant None: the library's autotuner picks the kernel variant (untimed)."""
+    variant None: the library's autotuner picks the kernel variant (untimed).  With `check`, the
+    timed steps start again from the initial field and check(final field) is returned as well."""
     import torch
     s = P.Solver.from_spec(spec, prec=prec)
     if stencil:
         s.stencil = stencil
     s.set_field(spec.psi0)
-    dt = 0.5 * s.max_dt()
+    if dt is None:
+        dt = 0.5 * s.max_dt()
     if variant is None:
-        variant = s.autotune(reps=20)
+        variant = s.autotune(reps=100)   # 2 x 100 steps of every variant: stable choice
     else:
         s.variant = variant
     s.step(warmup, dt)
+    if check is not None:
+        s.set_field(spec.psi0)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -114,7 +118,10 @@ def time_solver(P, spec, prec, steps, warmup, variant=None, stencil=None):
     ms = e0.elapsed_time(e1)
     mass = s.mass()
     launches = s.launches_per_step() * steps
+    checked = check(s.get_field()) if check is not None else None
     s.close()
+    if check is not None:
+        return ms, wall, launches, dt, mass, variant, checked
     return ms, wall, launches, dt, mass, variant
 
 
@@ -485,9 +492,28 @@ def main():
     precs = args.precs.split(",")
     force2d, force_stage = parse_variants(args.variant2d), parse_variants(args.stage_variant)
     res = {}
+    # The full benchmark run (2000 steps at 2049^2) has a stored FP64 oracle state, sampled at 545
+    # nodes (tests/golden/gp2d_2048_2000steps.json, written by the oracle alone): each precision's
+    # timed run starts from the initial field with the oracle's dt and is compared with it.
+    golden, check = None, None
+    gpath = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "gp2d_2048_2000steps.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            golden = json.load(f)
+        if golden["n"] != args.n or golden["steps"] != args.steps:
+            golden = None
+    if golden is not None:
+        iy, ix = np.array(golden["nodes"]).T
+        gref = np.array(golden["re"]) + 1j * np.array(golden["im"])
+
+        def check(field):
+            got = np.asarray(field, np.complex128)[iy, ix]
+            return float(np.linalg.norm(got - gref) / np.linalg.norm(gref))
     for prec in precs:
-        ms, wall, launches, dt, mass, variant = time_solver(P, spec, prec, args.steps, args.warmup,
-                                                            variant=force2d.get(prec))
+        timed = time_solver(P, spec, prec, args.steps, args.warmup, variant=force2d.get(prec),
+                            dt=golden["dt"] if golden else None, check=check)
+        ms, wall, launches, dt, mass, variant = timed[:6]
+        err = timed[6] if len(timed) > 6 else None
         gpts = npts * args.steps / (ms * 1e-3) / 1e9
         avg_launch_s = ms * 1e-3 / launches
         whole = launches == args.steps
@@ -516,7 +542,12 @@ def main():
                     "avg_launch_us": avg_launch_s * 1e6, "tile_variant": variant}
             note = f"{achieved:.0f} GB/s algorithmic ({100 * roof['frac']:.1f}% of HBM peak)"
         res[prec] = {"value": gpts, "ms_per_step": ms / args.steps, "wall_s": wall, "dt": dt, "mass_end": mass,
-                     "launches_per_step": launches // args.steps, "roofline": roof}
+                     "launches_per_step": launches // args.steps, "roofline": roof,
+                     "rel_l2_vs_fp64_oracle": err,
+                     "accuracy_check": ("sampled relative L2 (545 nodes) against the stored FP64 oracle state "
+                                        "after the same 2000 steps" if err is not None else None)}
+        if err is not None:
+            note += f", rel L2 vs FP64 oracle {err:.2e}"
         print(f"[bench] {prec}: {gpts:.2f} Gpt*steps/s, {ms / args.steps:.4f} ms/step, {note}",
               file=sys.stderr, flush=True)
         # the four-launch stage kernels on the same workload, with their HBM roofline
@@ -564,7 +595,10 @@ def main():
                    "precision": main_prec, "parallelism": "single GPU"},
         "roofline": res[main_prec]["roofline"],
         "stage_kernels": res[main_prec]["stage_kernels"],
-        "variants": {p: {k: v for k, v in r.items() if k in ("value", "ms_per_step", "roofline", "stage_kernels")}
+        "rel_l2_vs_fp64_oracle": res[main_prec]["rel_l2_vs_fp64_oracle"],
+        "accuracy_check": res[main_prec]["accuracy_check"],
+        "variants": {p: {k: v for k, v in r.items()
+                         if k in ("value", "ms_per_step", "roofline", "stage_kernels", "rel_l2_vs_fp64_oracle")}
                      for p, r in res.items() if p != main_prec},
     }
     try:
