@@ -291,6 +291,15 @@ def bench_3d(P, I, args):
                        "[-24,24]^3, Dirichlet 0, Thomas-Fermi cloud x vortex-ring phase",
            "interior_points": npts, "steps": args.steps3d}
     force3d = parse_variants(args.variant3d)
+    # config 3's full run (500 steps) has a stored FP64 oracle state sampled at 1241 nodes
+    # (tests/golden/gp3d_512_500steps.json, written by the oracle alone)
+    gold = None
+    gpath = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "gp3d_512_500steps.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            gold = json.load(f)
+        if gold["n"] != args.n3d:
+            gold = None
     for prec in args.precs3d.split(","):
         ms, wall, launches, dt, mass, variant = time_solver(P, spec, prec, args.steps3d, 5, variant=force3d.get(prec))
         gpts = npts * args.steps3d / (ms * 1e-3) / 1e9
@@ -309,9 +318,24 @@ def bench_3d(P, I, args):
                                   "algorithmic_bytes_per_launch": per_launch_bytes,
                                   "stage_equivalent_gbs": stage_eq, "stage_equivalent_frac": stage_eq / HBM_PEAK_GBS,
                                   "avg_launch_us": ms * 1e3 / launches, "tile_variant": variant}}
+        if gold is not None:   # the full run again from the initial field, outside any timed region
+            s = P.Solver.from_spec(spec, prec=prec)
+            s.set_field(spec.psi0)
+            s.variant = variant
+            s.step(gold["steps"], gold["dt"])
+            iz, iy, ix = np.array(gold["nodes"]).T
+            ref = np.array(gold["re"]) + 1j * np.array(gold["im"])
+            got = np.asarray(s.get_field())[iz, iy, ix].astype(np.complex128)
+            s.close()
+            res[prec]["rel_l2_vs_fp64_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            res[prec]["accuracy_check"] = ("sampled relative L2 (1241 nodes) against the stored FP64 oracle "
+                                           f"state after the full {gold['steps']}-step run")
         print(f"[bench] 3D {prec}: {gpts:.2f} Gpt*steps/s, {ms / args.steps3d:.3f} ms/step, {lps} launches/step, "
               f"{achieved:.0f} GB/s algorithmic ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak; "
               f"{stage_eq:.0f} GB/s in the four-launch form's bytes)", file=sys.stderr, flush=True)
+        if "rel_l2_vs_fp64_oracle" in res[prec]:
+            print(f"[bench] 3D {prec} full {gold['steps']}-step run: rel L2 vs FP64 oracle "
+                  f"{res[prec]['rel_l2_vs_fp64_oracle']:.2e}", file=sys.stderr, flush=True)
         if pairs and not args.no_stage3d:   # the four-launch stage kernels on the same workload, for comparison
             sv = min(range(4), key=lambda v: time_solver(P, spec, prec, 20, 2, variant=v)[0])
             ms_s, _, launches_s, _, _, _ = time_solver(P, spec, prec, args.steps3d, 5, variant=sv)

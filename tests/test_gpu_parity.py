@@ -321,6 +321,39 @@ def test_3d_config3_parity_run(gpu, gp3d_128_ref, prec):
     assert s.mass() == pytest.approx(P.mass(ref), rel=1e-5)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+def test_3d_config3_full_run_vs_stored_oracle(gpu, prec):
+    """Config 3's whole run: 513^3 nodes, 500 RK4 steps at dt = 0.5 k_max, in the autotuned launch
+    configuration, against the FP64 oracle's state sampled at 1241 nodes
+    (tests/golden/make_gp3d_full_run.py writes it from the oracle alone) and its mass."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "gp3d_512_500steps.json")
+    with open(path) as f:
+        gold = json.load(f)
+    sp = I.config_gp3d(n=gold["n"])
+    s = gpu.Solver.from_spec(sp, prec=prec)
+    s.set_field(sp.psi0)
+    v = s.autotune(reps=3)
+    say(f"[case] 513^3 {prec} variant {v}, {gold['steps']} steps at dt {gold['dt']:.9g}")
+    s.step(gold["steps"], gold["dt"])
+    g = np.asarray(s.get_field())
+    mass = s.mass()
+    s.close()
+    iz, iy, ix = np.array(gold["nodes"]).T
+    ref = np.array(gold["re"]) + 1j * np.array(gold["im"])
+    got = g[iz, iy, ix].astype(np.complex128)
+    del g
+    e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    em = abs(mass - gold["mass"]) / gold["mass"]
+    say(f"[result] 513^3 {prec} full run: sampled rel L2 {e:.3e}, mass {em:.3e}")
+    assert e <= TOL[prec]
+    # The oracle adds the 1.35e8 terms of the mass one after another (rounding error up to about
+    # n * 1.1e-16 relative); the GPU reduces them in a fixed tree.  The two sums of the same field
+    # therefore differ by more than the fields do.
+    assert em <= (1e-10 if prec == "f64" else 1e-5)
+
+
 def test_3d_full_size_sampled(gpu, orc):
     """513^3 (config 3's full size) in the benchmark's launch configuration: one RK4 step on the
     GPU, each sampled node checked against the oracle run on the node's dependency patch
