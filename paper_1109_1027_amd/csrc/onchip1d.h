@@ -17,6 +17,10 @@
 //   4. Lap (Eq. 2shoc1d2) and F on interior nodes; boundary F_b: Dirichlet 0
 //      (Eq. dbc_ut) or MSD i Im(F_{b-1}/Psi_{b-1}) Psi_b (Eq. msdbc_ut);
 //   5. the RK4 array operations of the stage (Eq. RK4) on every node that moves.
+// The alternative Laplacians (Dirichlet only) replace steps 2-4: CD takes D itself;
+// the non-compact five-point stencil exchanges two end nodes per side in step 1
+// and forms every slot's Laplacian before step 5 overwrites the slots it reads.
+// Either keeps the second barrier of the stage.
 #pragma once
 
 #include "dpp.h"
