@@ -118,7 +118,7 @@ struct Field {
 // The face value D^a_b at the face node b (normal to a, on no other face): the MSD step-1
 // value of Eq. msdbc_lap, from the full step-1 value at b-1, minus the second differences
 // along the face.
-template <typename IN, typename R>
+template <typename IN, typename R, int DIM>
 __device__ __forceinline__ C<R> face_closure(const Field<IN, R> &f, const Coeffs &cf, int a, const Node &b)
 {
     const Layout &L = f.L;
@@ -128,15 +128,14 @@ __device__ __forceinline__ C<R> face_closure(const Field<IN, R> &f, const Coeffs
     const C<R> ub = f.psi(b), uq = f.psi(q);
     C<R> Dq = czero<R>();   // the full step-1 value at b-1 (Eqs. 2d2shocs1, 3d2shocs)
 #pragma unroll
-    for (int t = 0; t < 3; ++t)
-        if (t < L.dim) Dq = cadd<R>(Dq, f.d2a(q, t, ih2));
+    for (int t = 0; t < DIM; ++t) Dq = cadd<R>(Dq, f.d2a(q, t, ih2));
     const R den = uq.x * uq.x + uq.y * uq.y;
     const R ratio = den != R(0) ? (Dq.x * uq.x + Dq.y * uq.y) / den : R(0);
     const R fac = ratio + (nonlin<R>(uq, f.pot(q), s) - nonlin<R>(ub, f.pot(b), s)) * (R)cf.ia;
     C<R> Db = mk<R>(fac * ub.x, fac * ub.y);   // Lap_b
 #pragma unroll
-    for (int t = 0; t < 3; ++t)
-        if (t < L.dim && t != a) Db = csub<R>(Db, f.d2a(b, t, ih2));
+    for (int t = 0; t < DIM; ++t)
+        if (t != a) Db = csub<R>(Db, f.d2a(b, t, ih2));
     return Db;
 }
 
@@ -153,18 +152,18 @@ struct StoredFaces {
 };
 
 // ... or formed from the field on the spot (while another thread may be writing the arrays).
-template <typename IN, typename R>
+template <typename IN, typename R, int DIM>
 struct DirectFaces {
     Field<IN, R> f;
     Coeffs cf;
-    __device__ __forceinline__ C<R> operator()(int a, const Node &r) const { return face_closure<IN, R>(f, cf, a, r); }
+    __device__ __forceinline__ C<R> operator()(int a, const Node &r) const { return face_closure<IN, R, DIM>(f, cf, a, r); }
 };
 
 // ... or, for the thread that has just formed the value at its own face node b, that value
 // there and formed on the spot elsewhere.
-template <typename IN, typename R>
+template <typename IN, typename R, int DIM>
 struct KnownFace {
-    DirectFaces<IN, R> direct;
+    DirectFaces<IN, R, DIM> direct;
     int a;
     Node b;
     C<R> value;
@@ -178,7 +177,7 @@ struct KnownFace {
 
 // F at the interior node q, per-axis 2SHOC (Eqs. 2d2shocMs1-2, 3d2shocMs1-2) with the face
 // values where q's neighbour along an axis is a boundary node.
-template <typename IN, typename R, typename Faces>
+template <typename IN, typename R, int DIM, typename Faces>
 __device__ C<R> interior_F(const Field<IN, R> &f, const Faces &face_value, const Coeffs &cf, const Node &q)
 {
     const R ih2 = (R)cf.ih2, c76 = (R)cf.c76, c112 = (R)cf.c112;
@@ -186,14 +185,14 @@ __device__ C<R> interior_F(const Field<IN, R> &f, const Faces &face_value, const
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         dc[a] = dl[a] = dr[a] = czero<R>();
-        if (a >= f.L.dim) continue;
+        if (a >= DIM) continue;
         dc[a] = f.d2a(q, a, ih2);
         const Node lo = step(q, a, -1), hi = step(q, a, 1);
         dl[a] = lo.at(a) == 0 ? face_value(a, lo) : f.d2a(lo, a, ih2);
         dr[a] = hi.at(a) == ext(f.L, a) ? face_value(a, hi) : f.d2a(hi, a, ih2);
     }
     C<R> lap;
-    if (f.L.dim == 2) {
+    if constexpr (DIM == 2) {
         lap = lap2<R>(dc[0], dc[1], dl[0], dr[0], dl[1], dr[1], c76, c112);
     } else {
         lap = lap3<R>(dc[0], dc[1], dc[2], dl[0], dr[0], dl[1], dr[1], dl[2], dr[2], c76, c112);
@@ -211,7 +210,7 @@ __device__ __forceinline__ R phase_rate(const C<R> &F, const C<R> &u)
 
 // ---- 1. face values D^a_b from the stage input -------------------------------------------
 
-template <typename IN, typename R>
+template <typename IN, typename R, int DIM>
 __global__ void msd_face_kernel(Field<IN, R> f, Coeffs cf, C<R> *DBx, C<R> *DBy, C<R> *DBz)
 {
     const int a = blockIdx.y, side = blockIdx.z;
@@ -224,7 +223,7 @@ __global__ void msd_face_kernel(Field<IN, R> f, Coeffs cf, C<R> *DBx, C<R> *DBy,
     for (int t = 0; t < 3; ++t)
         if (t != a && on_bnd(L, b, t)) return;   // edge / corner: never read by the stage kernels
     C<R> *dst = a == 0 ? DBx : a == 1 ? DBy : DBz;
-    dst[side * face_size(L, a) + fi] = face_closure<IN, R>(f, cf, a, b);
+    dst[side * face_size(L, a) + fi] = face_closure<IN, R, DIM>(f, cf, a, b);
 }
 
 template <typename IN, typename R>
@@ -240,8 +239,12 @@ static hipError_t launch_faces(const void *in, const void *V, const Layout &L, c
     }
     Field<IN, R> f{(const C<IN> *)in, (const R *)V, L};
     dim3 grid((unsigned)((maxf + 255) / 256), (unsigned)L.dim, 2);
-    hipLaunchKernelGGL((msd_face_kernel<IN, R>), grid, dim3(256), 0, st, f, c, (C<R> *)DB[0], (C<R> *)DB[1],
-                       (C<R> *)DB[2]);
+    if (L.dim == 3)
+        hipLaunchKernelGGL((msd_face_kernel<IN, R, 3>), grid, dim3(256), 0, st, f, c, (C<R> *)DB[0], (C<R> *)DB[1],
+                           (C<R> *)DB[2]);
+    else
+        hipLaunchKernelGGL((msd_face_kernel<IN, R, 2>), grid, dim3(256), 0, st, f, c, (C<R> *)DB[0], (C<R> *)DB[1],
+                           (C<R> *)DB[2]);
     return hipGetLastError();
 }
 
@@ -256,46 +259,60 @@ __device__ __forceinline__ bool owner(const Layout &L, const Node &b, int a)
     return true;
 }
 
-template <typename IN, typename R, typename M>
+// Every load of a thread is issued before its first store: a store in between would make
+// the compiler keep the loads behind it (the arrays may alias, as far as it knows) and so
+// add a memory round trip per group of loads to a launch that is all latency.
+template <typename IN, typename R, typename M, int DIM>
 __global__ void msd_stage_kernel(Field<IN, R> f, StageArgs A, C<R> *DBx, C<R> *DBy, C<R> *DBz)
 {
     const int a = blockIdx.y, side = blockIdx.z;
     const Layout &L = f.L;
-    if (a >= L.dim) return;
+    if (a >= DIM) return;
     const int64_t fi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (fi >= face_size(L, a)) return;
     const Node b = face_node(L, a, side, fi);
     bool face = true;   // on no other face: the interior launch reads its D^a_b
 #pragma unroll
-    for (int t = 0; t < 3; ++t)
+    for (int t = 0; t < DIM; ++t)
         if (t != a && on_bnd(L, b, t)) face = false;
-    const DirectFaces<IN, R> direct{f, A.c};
-    KnownFace<IN, R> faces{direct, a, b, czero<R>(), false};
-    if (face) {
-        faces.value = direct(a, b);
-        faces.known = true;
-        C<R> *dst = a == 0 ? DBx : a == 1 ? DBy : DBz;
-        dst[side * face_size(L, a) + fi] = faces.value;
-    }
-    if (!owner(L, b, a)) return;
-    const Node q = inner(L, b);
-    const C<R> uq = f.psi(q), ub = f.psi(b);
-    const R w = phase_rate<R>(interior_F<IN, R>(f, faces, A.c, q), uq);
-    const C<R> F = mk<R>(-w * ub.y, w * ub.x);
+    const bool own = owner(L, b, a);
     const int64_t p = L.idx(b.x, b.y, b.z);
-    const R ck = (R)A.c.ck;
     C<M> *psin = (C<M> *)A.psin;
     C<R> *K = (C<R> *)A.K;
     C<R> *out = (C<R> *)A.out;
+    C<M> pn = mk<M>(M(0), M(0));
+    C<R> kt = czero<R>();
+    if (own && (A.stage >= 2 || !same_m<IN, R>::v)) pn = psin[p];
+    if (own && A.stage >= 2) kt = K[p];
+    const DirectFaces<IN, R, DIM> direct{f, A.c};
+    KnownFace<IN, R, DIM> faces{direct, a, b, czero<R>(), false};
+    if (face) {
+        faces.value = direct(a, b);
+        faces.known = true;
+    }
+    C<R> F = czero<R>(), ub = czero<R>();
+    if (own) {
+        const Node q = inner(L, b);
+        const C<R> uq = f.psi(q);
+        ub = f.psi(b);
+        const R w = phase_rate<R>(interior_F<IN, R, DIM>(f, faces, A.c, q), uq);
+        F = mk<R>(-w * ub.y, w * ub.x);
+    }
+    if (face) {
+        C<R> *dst = a == 0 ? DBx : a == 1 ? DBy : DBz;
+        dst[side * face_size(L, a) + fi] = faces.value;
+    }
+    if (!own) return;
+    const R ck = (R)A.c.ck;
     if (A.stage == 1) {
-        const C<M> base = same_m<IN, R>::v ? cvt<M, R>(ub) : psin[p];
+        const C<M> base = same_m<IN, R>::v ? cvt<M, R>(ub) : pn;
         K[p] = F;
         out[p] = cvt<R, M>(axpy_m<R, M>(base, ck, F));
     } else if (A.stage <= 3) {
-        K[p] = kacc<R>(K[p], F);
-        out[p] = cvt<R, M>(axpy_m<R, M>(psin[p], ck, F));
+        K[p] = kacc<R>(kt, F);
+        out[p] = cvt<R, M>(axpy_m<R, M>(pn, ck, F));
     } else {
-        psin[p] = axpy_m<R, M>(psin[p], ck, cadd<R>(K[p], F));
+        psin[p] = axpy_m<R, M>(pn, ck, cadd<R>(kt, F));
     }
 }
 
@@ -312,14 +329,18 @@ static hipError_t launch_stage_bnd(const StageArgs &A, void *const DB[3], hipStr
     }
     Field<IN, R> f{(const C<IN> *)A.in, (const R *)A.V, L};
     dim3 grid((unsigned)((maxf + 255) / 256), (unsigned)L.dim, 2);
-    hipLaunchKernelGGL((msd_stage_kernel<IN, R, M>), grid, dim3(256), 0, st, f, A, (C<R> *)DB[0], (C<R> *)DB[1],
-                       (C<R> *)DB[2]);
+    if (L.dim == 3)
+        hipLaunchKernelGGL((msd_stage_kernel<IN, R, M, 3>), grid, dim3(256), 0, st, f, A, (C<R> *)DB[0],
+                           (C<R> *)DB[1], (C<R> *)DB[2]);
+    else
+        hipLaunchKernelGGL((msd_stage_kernel<IN, R, M, 2>), grid, dim3(256), 0, st, f, A, (C<R> *)DB[0],
+                           (C<R> *)DB[1], (C<R> *)DB[2]);
     return hipGetLastError();
 }
 
 // ---- the bound's boundary term: max over b-1 of (h^2/a) |F_{b-1} / Psi_{b-1}| -----------------
 
-template <typename IN, typename R>
+template <typename IN, typename R, int DIM>
 __global__ void msd_bound_kernel(Field<IN, R> f, Coeffs cf, const void *DB0, const void *DB1, const void *DB2,
                                  double h2a, unsigned long long *out)
 {
@@ -335,7 +356,7 @@ __global__ void msd_bound_kernel(Field<IN, R> f, Coeffs cf, const void *DB0, con
     const C<R> uq = f.psi(q);
     const double den = (double)uq.x * uq.x + (double)uq.y * uq.y;
     if (den == 0.0) return;
-    const C<R> F = interior_F<IN, R>(f, faces, cf, q);
+    const C<R> F = interior_F<IN, R, DIM>(f, faces, cf, q);
     const double B = h2a * sqrt(((double)F.x * F.x + (double)F.y * F.y) / den);
     // non-negative doubles order as their bit patterns: the maximum is exact and order-free
     atomicMax(out, (unsigned long long)__double_as_longlong(B));
@@ -380,19 +401,34 @@ hipError_t launch_msd_bound(Prec prec, const void *psin, const void *V, const vo
     unsigned long long *o = (unsigned long long *)dev_out;
     switch (prec) {
     case P_F64:
-        hipLaunchKernelGGL((msd_bound_kernel<double, double>), grid, dim3(256), 0, st,
-                           Field<double, double>{(const C<double> *)psin, (const double *)V, L}, c, DB[0], DB[1], DB[2],
-                           h2a, o);
+        if (L.dim == 3)
+            hipLaunchKernelGGL((msd_bound_kernel<double, double, 3>), grid, dim3(256), 0, st,
+                               Field<double, double>{(const C<double> *)psin, (const double *)V, L}, c, DB[0], DB[1], DB[2],
+                               h2a, o);
+        else
+            hipLaunchKernelGGL((msd_bound_kernel<double, double, 2>), grid, dim3(256), 0, st,
+                               Field<double, double>{(const C<double> *)psin, (const double *)V, L}, c, DB[0], DB[1], DB[2],
+                               h2a, o);
         break;
     case P_F32:
-        hipLaunchKernelGGL((msd_bound_kernel<float, float>), grid, dim3(256), 0, st,
-                           Field<float, float>{(const C<float> *)psin, (const float *)V, L}, c, DB[0], DB[1], DB[2],
-                           h2a, o);
+        if (L.dim == 3)
+            hipLaunchKernelGGL((msd_bound_kernel<float, float, 3>), grid, dim3(256), 0, st,
+                               Field<float, float>{(const C<float> *)psin, (const float *)V, L}, c, DB[0], DB[1], DB[2],
+                               h2a, o);
+        else
+            hipLaunchKernelGGL((msd_bound_kernel<float, float, 2>), grid, dim3(256), 0, st,
+                               Field<float, float>{(const C<float> *)psin, (const float *)V, L}, c, DB[0], DB[1], DB[2],
+                               h2a, o);
         break;
     default:
-        hipLaunchKernelGGL((msd_bound_kernel<double, float>), grid, dim3(256), 0, st,
-                           Field<double, float>{(const C<double> *)psin, (const float *)V, L}, c, DB[0], DB[1], DB[2],
-                           h2a, o);
+        if (L.dim == 3)
+            hipLaunchKernelGGL((msd_bound_kernel<double, float, 3>), grid, dim3(256), 0, st,
+                               Field<double, float>{(const C<double> *)psin, (const float *)V, L}, c, DB[0], DB[1], DB[2],
+                               h2a, o);
+        else
+            hipLaunchKernelGGL((msd_bound_kernel<double, float, 2>), grid, dim3(256), 0, st,
+                               Field<double, float>{(const C<double> *)psin, (const float *)V, L}, c, DB[0], DB[1], DB[2],
+                               h2a, o);
         break;
     }
     return hipGetLastError();
