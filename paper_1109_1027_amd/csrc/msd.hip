@@ -263,7 +263,7 @@ __device__ __forceinline__ bool owner(const Layout &L, const Node &b, int a)
 // the compiler keep the loads behind it (the arrays may alias, as far as it knows) and so
 // add a memory round trip per group of loads to a launch that is all latency.
 template <typename IN, typename R, typename M, int DIM>
-__global__ void msd_stage_kernel(Field<IN, R> f, StageArgs A, C<R> *DBx, C<R> *DBy, C<R> *DBz)
+__global__ __launch_bounds__(256) void msd_stage_kernel(Field<IN, R> f, StageArgs A, C<R> *DBx, C<R> *DBy, C<R> *DBz)
 {
     const int a = blockIdx.y, side = blockIdx.z;
     const Layout &L = f.L;
