@@ -121,7 +121,6 @@ struct Field {
 template <typename IN, typename R, int DIM>
 __device__ __forceinline__ C<R> face_closure(const Field<IN, R> &f, const Coeffs &cf, int a, const Node &b)
 {
-    const Layout &L = f.L;
     const int side = b.at(a) == 0 ? 0 : 1;
     const R ih2 = (R)cf.ih2, s = (R)cf.s;
     const Node q = step(b, a, side ? -1 : 1);
