@@ -267,7 +267,8 @@ __global__ __launch_bounds__(256) void msd_stage_kernel(Field<IN, R> f, StageArg
     const int a = blockIdx.y, side = blockIdx.z;
     const Layout &L = f.L;
     if (a >= DIM) return;
-    const int64_t fi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    // consecutive face rows on one XCD, whose L2 then holds the rows that neighbours share
+    const int64_t fi = xcd_remap(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
     if (fi >= face_size(L, a)) return;
     const Node b = face_node(L, a, side, fi);
     bool face = true;   // on no other face: the interior launch reads its D^a_b
