@@ -328,12 +328,15 @@ static hipError_t launch_stage_bnd(const StageArgs &A, void *const DB[3], hipStr
         if (f > maxf) maxf = f;
     }
     Field<IN, R> f{(const C<IN> *)A.in, (const R *)A.V, L};
-    dim3 grid((unsigned)((maxf + 255) / 256), (unsigned)L.dim, 2);
+    // a 2D boundary has a few thousand nodes and the launch is latency: one-wave blocks spread
+    // them over four times as many CUs
+    const int bs = L.dim == 3 ? 256 : 64;
+    dim3 grid((unsigned)((maxf + bs - 1) / bs), (unsigned)L.dim, 2);
     if (L.dim == 3)
-        hipLaunchKernelGGL((msd_stage_kernel<IN, R, M, 3>), grid, dim3(256), 0, st, f, A, (C<R> *)DB[0],
+        hipLaunchKernelGGL((msd_stage_kernel<IN, R, M, 3>), grid, dim3(bs), 0, st, f, A, (C<R> *)DB[0],
                            (C<R> *)DB[1], (C<R> *)DB[2]);
     else
-        hipLaunchKernelGGL((msd_stage_kernel<IN, R, M, 2>), grid, dim3(256), 0, st, f, A, (C<R> *)DB[0],
+        hipLaunchKernelGGL((msd_stage_kernel<IN, R, M, 2>), grid, dim3(bs), 0, st, f, A, (C<R> *)DB[0],
                            (C<R> *)DB[1], (C<R> *)DB[2]);
     return hipGetLastError();
 }
