@@ -100,6 +100,23 @@ def test_msd_2d_non_square_dark_plane(gpu, orc):
     sol.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("width", [7.875, 0.5])
+def test_msd_2d_faces_filling_whole_blocks(gpu, orc, prec, width):
+    """The 2D boundary launch runs one-wave blocks: faces of exactly 64 and 128 nodes (no partial
+    block), and a 5-node face (less than one block), on a perturbed dark plane."""
+    h = 0.125
+    n, psi = I.dark_plane(2, h, lo=-8.0, hi=7.875, width=width)   # 127 x 63 or 127 x 4 intervals
+    rng = np.random.default_rng(5)
+    psi = psi + 1e-3 * (rng.standard_normal(psi.shape) + 1j * rng.standard_normal(psi.shape))
+    P = orc.Problem(2, n, h, 0.5, -1.0, bc="msd")
+    dt = 0.5 * P.max_dt(psi)
+    say(f"[case] msd 2d whole-block faces n={n} {prec}")
+    out, sol = gpu_run(gpu, 2, n, h, psi, prec, 20, dt)
+    sol.close()
+    assert rel(out, P.rk4(psi, 20, dt)) <= TOL[prec]
+
+
 def test_msd_3d_non_cubic(gpu, orc):
     n, psi = I.dark_plane(3, 0.25, width=1.5)   # 64 x 6 x 6 intervals
     P = orc.Problem(3, n, 0.25, 0.5, -1.0, bc="msd")
