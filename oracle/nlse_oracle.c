@@ -215,22 +215,39 @@ static void step2_single(const orc_problem *P, const geom *g, const zd *psi, con
             }
 }
 
+/* Per-axis step-1 value on a face node q normal to axis a, the boundary closure of the
+ * per-axis forms.  The paper gives no rule for D^a on the boundary.  This oracle takes the
+ * step-1 boundary value of q (Eq. dbc_lap or Eq. msdbc_lap, held in Dfull) minus the
+ * central differences along the face, so that the D^a of q sum to the single-storage
+ * boundary value.  q must lie on exactly one boundary (its tangential neighbours exist). */
+static zd face_value(const orc_problem *P, const geom *g, const zd *psi, const zd *Dfull, long q, int a)
+{
+    const double ih2 = 1.0 / (P->h * P->h);
+    zd tang = 0.0;
+    for (int b = 0; b < P->dim; ++b)
+        if (b != a) tang += ih2 * (psi[q + g->st[b]] - 2.0 * psi[q] + psi[q - g->st[b]]);
+    return Dfull[q] - tang;
+}
+
+/* The full step-1 array: interior differences and the boundary closure. */
+static zd *step1_full(const orc_problem *P, const geom *g, const zd *psi)
+{
+    zd *Dfull = calloc((size_t)g->total, sizeof(zd));
+    step1_interior(P, g, psi, Dfull);
+    step1_boundary(P, g, psi, Dfull);
+    return Dfull;
+}
+
 /* Per-axis (multi-storage) 2SHOC (Eq. 2d2shocMs1-2, Eq. 3d2shocMs1-2):
- *   D^a = delta_a^2 Psi,  Lap = sum_a [ (7/6) D^a - (1/12)(D^a_{+a} + D^a_{-a}) ].
- * The paper gives no boundary rule for D^a.  On a face node q normal to axis a
- * this oracle takes D^a_q = Lap_b(q) - sum_{b != a} delta_b^2 Psi_q: the step-1
- * boundary value (Eq. dbc_lap) minus the central differences along the face,
- * so that sum_a D^a_q equals the single-storage boundary value.  Only D^a on
- * faces normal to a is ever read. */
+ *   D^a = delta_a^2 Psi,  Lap = sum_a [ (7/6) D^a - (1/12)(D^a_{+a} + D^a_{-a}) ],
+ * with D^a on a face node normal to a from face_value.  Only D^a on faces normal to
+ * a is ever read. */
 static void lap_per_axis(const orc_problem *P, const geom *g, const zd *psi, zd *lap)
 {
     const double ih2 = 1.0 / (P->h * P->h), c76 = 7.0 / 6.0, c112 = 1.0 / 12.0;
     zd *Da[3] = {NULL, NULL, NULL};
     for (int a = 0; a < P->dim; ++a) Da[a] = calloc((size_t)g->total, sizeof(zd));
-    zd *Dfull = calloc((size_t)g->total, sizeof(zd));
-    /* full step-1 array: its boundary entries are the step-1 closure Lap_b */
-    step1_interior(P, g, psi, Dfull);
-    step1_boundary(P, g, psi, Dfull);
+    zd *Dfull = step1_full(P, g, psi);
     for (long p = 0; p < g->total; ++p) {
         long idx[3];
         coords_of(g, p, idx);
@@ -241,10 +258,7 @@ static void lap_per_axis(const orc_problem *P, const geom *g, const zd *psi, zd 
             for (int a = 0; a < P->dim; ++a)
                 Da[a][p] = ih2 * (psi[p + g->st[a]] - 2.0 * psi[p] + psi[p - g->st[a]]);
         } else if (nb == 1) {
-            zd tang = 0.0;
-            for (int b = 0; b < P->dim; ++b)
-                if (b != bax) tang += ih2 * (psi[p + g->st[b]] - 2.0 * psi[p] + psi[p - g->st[b]]);
-            Da[bax][p] = Dfull[p] - tang;
+            Da[bax][p] = face_value(P, g, psi, Dfull, p, bax);
         }
     }
     for (long p = 0; p < g->total; ++p) {
@@ -262,17 +276,25 @@ static void lap_per_axis(const orc_problem *P, const geom *g, const zd *psi, zd 
     free(Dfull);
 }
 
-/* Value of Psi along axis a at offset off from node p, with the odd reflection
- * Psi_{-1} = 2 Psi_0 - Psi_1 beyond a boundary node (the ghost that makes the
- * second difference vanish on the boundary). */
-static zd along(const orc_problem *P, const geom *g, const zd *psi, long p, const long idx[3], int a, int off)
+/* Value of Psi along axis a at offset off from the interior node p.  One node beyond a
+ * boundary node b it is the ghost Psi_{b-+1} = 2 Psi_b - Psi_{b+-1} + h^2 D^a_b, the value
+ * whose second difference at b is the step-1 boundary value D^a_b (face_value, from Eq.
+ * dbc_lap): with it the five-point stencil next to the boundary is exactly the 2SHOC
+ * combination (7/6) D^a - (1/12)(neighbouring D^a) that Sec. 2.1 shows it equals.  With zero
+ * boundary values D^a_b = 0 and the ghost is the odd reflection. */
+static zd along(const orc_problem *P, const geom *g, const zd *psi, const zd *Dfull, long p, const long idx[3],
+                int a, int off)
 {
     long t = idx[a] + off;
     long st = g->st[a];
-    if (t < 0) return 2.0 * psi[p - idx[a] * st] - psi[p - idx[a] * st + st];
+    const double h2 = P->h * P->h;
+    if (t < 0) {
+        long pb = p - idx[a] * st;
+        return 2.0 * psi[pb] - psi[pb + st] + h2 * face_value(P, g, psi, Dfull, pb, a);
+    }
     if (t > P->n[a]) {
         long pb = p + (P->n[a] - idx[a]) * st;
-        return 2.0 * psi[pb] - psi[pb - st];
+        return 2.0 * psi[pb] - psi[pb - st] + h2 * face_value(P, g, psi, Dfull, pb, a);
     }
     return psi[p + off * st];
 }
@@ -282,18 +304,20 @@ static zd along(const orc_problem *P, const geom *g, const zd *psi, long p, cons
 static void lap_noncompact(const orc_problem *P, const geom *g, const zd *psi, zd *lap)
 {
     const double i12h2 = 1.0 / (12.0 * P->h * P->h);
+    zd *Dfull = step1_full(P, g, psi);
     for (long p = 0; p < g->total; ++p) {
         long idx[3];
         coords_of(g, p, idx);
         if (!is_interior(P, idx)) continue;
         zd acc = 0.0;
         for (int a = 0; a < P->dim; ++a) {
-            zd m2 = along(P, g, psi, p, idx, a, -2), p2 = along(P, g, psi, p, idx, a, 2);
+            zd m2 = along(P, g, psi, Dfull, p, idx, a, -2), p2 = along(P, g, psi, Dfull, p, idx, a, 2);
             acc += i12h2 * (-p2 + 16.0 * psi[p + g->st[a]] - 30.0 * psi[p]
                             + 16.0 * psi[p - g->st[a]] - m2);
         }
         lap[p] = acc;
     }
+    free(Dfull);
 }
 
 /* Laplacian of the chosen form on every interior node (boundary entries untouched). */

@@ -158,6 +158,20 @@ def test_2shoc_equals_noncompact_odd_ghosts(orc, dim, n):
     np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * np.abs(a).max())
 
 
+@pytest.mark.parametrize("dim,n", [(1, 33), (2, 17), (3, 9)])
+def test_2shoc_equals_noncompact_any_dirichlet(orc, dim, n):
+    """Sec. 2.1: the two-step scheme is the five-point fourth-order stencil.  Next to a boundary
+    node b the five-point stencil reads one node beyond b; the ghost 2 Psi_b - Psi_{b+-1} +
+    h^2 D^a_b has the step-1 boundary value D^a_b (Eq. dbc_lap) as its second difference at b,
+    so the two agree to round-off for arbitrary Dirichlet values, s and V as well."""
+    h = 0.4
+    f = rand_field((n + 1,) * dim, zero_boundary=False)
+    V = rng.uniform(-1, 2, (n + 1,) * dim)
+    a = orc.Problem(dim, n, h, 0.6, -1.7, V, lap="2shoc").laplacian(f)
+    b = orc.Problem(dim, n, h, 0.6, -1.7, V, lap="noncompact").laplacian(f)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * np.abs(a).max())
+
+
 def test_cd_is_second_difference(orc):
     n, h = 12, 0.5
     f = rand_field((n + 1, n + 1))
@@ -179,21 +193,24 @@ def test_cd_quartic_closed_form(orc, dim, n):
 
 
 @pytest.mark.parametrize("dim,n", [(1, 9), (2, 8), (3, 6)])
-def test_noncompact_odd_ghost_closed_form(orc, dim, n):
-    """Odd reflection ghosts with non-zero boundary values.  With x_a measured from the lower
-    boundary, the ghost of x^2 is 2 f(0) - f(h) = -h^2 below and the true value - 2 h^2
-    above, so the five-point difference gives 2 deep inside and 26/12 next to either face of
-    that axis; linear terms and constants reflect exactly.  Hence for
-    f = sum_a (x_a^2 + c_a x_a) + c0:  Lap = 2 d + (2/12) (number of axes on which the node
-    is next to a face)."""
+def test_noncompact_ghost_closed_form(orc, dim, n):
+    """Ghosts with non-zero boundary values, in closed form.  For f = c (sum_a (x_a^2 + c_a x_a)
+    + c0) with s = V = 0, Eq. dbc_lap gives Lap_b = 0 on every boundary node, so on a face node
+    normal to axis a the per-axis value is D^a_b = 0 - (second differences along the face) =
+    -2 c (d - 1) (each tangential x_b^2 differences to 2 c exactly).  The ghost's second
+    difference at b is that value, so along an axis on which the node is next to a face the
+    five-point difference is (7/6) 2c - (1/12)(2c + D^a_b) = 2c (12 + d)/12 (linear terms and
+    constants difference to zero), and 2c deep inside.  Hence
+    Lap = c [2 d + (2 d / 12) (number of axes on which the node is next to a face)]."""
     h = 0.3
     ii = np.indices((n + 1,) * dim)
     xs = ii.astype(float) * h
-    c = np.array([0.7, -1.1, 0.4][:dim])
-    f = (np.sum(xs ** 2, axis=0) + np.tensordot(c, xs, axes=1) + 2.5) * (0.8 + 0.3j)
+    cf = np.array([0.7, -1.1, 0.4][:dim])
+    c = 0.8 + 0.3j
+    f = (np.sum(xs ** 2, axis=0) + np.tensordot(cf, xs, axes=1) + 2.5) * c
     out = orc.Problem(dim, n, h, 1.0, 0.0, lap="noncompact").laplacian(f)
     near = np.sum((ii == 1) | (ii == n - 1), axis=0)
-    ref = (2.0 * dim + (2.0 / 12.0) * near) * (0.8 + 0.3j)
+    ref = (2.0 * dim + (2.0 * dim / 12.0) * near) * c
     np.testing.assert_allclose(inner(out, dim, 1), inner(ref, dim, 1), rtol=1e-11, atol=1e-11)
 
 
