@@ -76,8 +76,10 @@ typedef enum {
 typedef enum {
     NLSE_STENCIL_2SHOC = 0,       /* the two-step compact scheme (Sec. 2), the default */
     NLSE_STENCIL_NONCOMPACT = 1,  /* non-compact fourth-order stencil per axis, the scheme 2SHOC
-                                     is compared with (Sec. 2.1, Sec. 5); beyond the boundary it
-                                     reads the odd reflection 2 Psi_b - Psi_{b+-1} */
+                                     is compared with (Sec. 2.1, Sec. 5); one node beyond a
+                                     boundary node b it reads the ghost 2 Psi_b - Psi_{b+-1}
+                                     + h^2 D^a_b, D^a_b the step-1 face value of Eq. dbc_lap,
+                                     so it equals 2SHOC up to rounding for any Dirichlet data */
     NLSE_STENCIL_CD = 2           /* second-order central difference (Sec. 3.1's CD) */
 } nlse_stencil;
 

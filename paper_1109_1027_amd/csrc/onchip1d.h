@@ -94,8 +94,8 @@ __device__ __forceinline__ void exchange1d2(const C<R> (&v)[NPT], int npt, int l
     }
 }
 
-// ST selects the Laplacian: 0 2SHOC, 1 the non-compact five-point stencil (odd-reflection
-// ghosts beyond the boundary), 2 the second-order CD; the alternatives with Dirichlet
+// ST selects the Laplacian: 0 2SHOC, 1 the non-compact five-point stencil (beyond a boundary
+// node b the ghost 2 Psi_b - Psi_{b-+1} + h^2 D_b, D_b of Eq. dbc_lap), 2 the second-order CD; the alternatives with Dirichlet
 // boundaries only.  Every path takes exactly two workgroup barriers per stage (the idle
 // waves below count on it).
 template <typename R, typename M, int BS, int NPT, int ST = 0>
@@ -116,7 +116,7 @@ __device__ void solve1d_onchip(const Solve1DArgs &A, unsigned char *smem_raw)
 
     const R a = (R)A.c.a, s = (R)A.c.s, ih2 = (R)A.c.ih2, c76 = (R)A.c.c76, c112 = (R)A.c.c112;
     const R ia = (R)A.c.ia;
-    const R i12h2 = (R)(A.c.ih2 / 12.0);
+    const R i12h2 = (R)(A.c.ih2 / 12.0), h2 = (R)(1.0 / A.c.ih2);
     const R k2 = (R)A.k2, kk = (R)A.k, k6 = (R)A.k6;
     C<M> *gpsi = (C<M> *)A.psin;
     const R *gV = (const R *)A.V;
@@ -224,8 +224,17 @@ __device__ void solve1d_onchip(const Solve1DArgs &A, unsigned char *smem_raw)
                     const C<R> q1 = j + 1 < npt ? U[j + 1 < NPT ? j + 1 : j] : un;
                     C<R> m2 = j >= 2 ? U[j > 1 ? j - 2 : 0] : (j == 1 ? up : up2);
                     C<R> q2 = j + 2 < npt ? U[j + 2 < NPT ? j + 2 : j] : (j + 1 < npt ? un : un2);
-                    if (i == 1) m2 = ghost<R>(m1, u);       // m1 is Psi_0
-                    if (i == n - 1) q2 = ghost<R>(q1, u);   // q1 is Psi_n
+                    // beyond node 0 or n the ghost carries h^2 D_b of Eq. dbc_lap; the boundary
+                    // node is the neighbouring slot of the same thread (slot j-1 for node 0,
+                    // j+1 for node n)
+                    if (i == 1) {         // m1 is Psi_0
+                        const R vb = Vv[j > 0 ? j - 1 : 0];
+                        m2 = ghost<R>(m1, u, cscale<R>(-nonlin<R>(m1, vb, s) * ia * h2, m1));
+                    }
+                    if (i == n - 1) {     // q1 is Psi_n
+                        const R vb = Vv[j + 1 < NPT ? j + 1 : j];
+                        q2 = ghost<R>(q1, u, cscale<R>(-nonlin<R>(q1, vb, s) * ia * h2, q1));
+                    }
                     D[j] = d4nc<R>(m2, m1, u, q1, q2, i12h2);
                 }
                 __syncthreads();

@@ -75,13 +75,16 @@ __device__ __forceinline__ C<R> d4nc(C<R> m2, C<R> m1, C<R> c, C<R> p1, C<R> p2,
     return mk<R>(tx * i12h2, ty * i12h2);
 }
 
-// Odd reflection across a boundary node b: the ghost value 2 Psi_b - Psi_{b-+1} that makes
-// the second difference vanish at b (the non-compact stencil's value one node outside).
+// Ghost value one node beyond a Dirichlet boundary node b for the non-compact stencil:
+// 2 Psi_b - Psi_{b-+1} + h^2 D^a_b (h2db = h^2 D^a_b), the value whose second difference at b
+// is the step-1 face value D^a_b of Eq. dbc_lap.  With it the five-point stencil next to the
+// boundary equals the 2SHOC combination there (Sec. 2.1); with zero boundary values it is
+// the odd reflection 2 Psi_b - Psi_{b-+1}.
 template <typename R>
-__device__ __forceinline__ C<R> ghost(C<R> b, C<R> inner)
+__device__ __forceinline__ C<R> ghost(C<R> b, C<R> inner, C<R> h2db)
 {
 #pragma clang fp contract(off)
-    return mk<R>(fmar(R(2), b.x, -inner.x), fmar(R(2), b.y, -inner.y));
+    return mk<R>(fmar(R(2), b.x, -inner.x) + h2db.x, fmar(R(2), b.y, -inner.y) + h2db.y);
 }
 
 // Step 2 of the 1D form (Sec. 2.1, Eq. 2shoc1d2): (7/6) D_i - (1/12)(D_{i+1} + D_{i-1}).

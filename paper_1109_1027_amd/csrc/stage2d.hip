@@ -28,8 +28,10 @@
 //
 // Alternative Laplacians for comparison (StageArgs::stencil): the non-compact
 // fourth-order stencil (-Psi_{+-2} + 16 Psi_{+-1} - 30 Psi) / (12 h^2) per axis,
-// the one 2SHOC is measured against in Sec. 2.1 and Sec. 5, with odd-reflection
-// ghosts 2 Psi_b - Psi_{b+-1} one node beyond the boundary; and the second-order
+// the one 2SHOC is measured against in Sec. 2.1 and Sec. 5, with the ghosts
+// 2 Psi_b - Psi_{b+-1} + h^2 D^a_b one node beyond a face (their second difference at b
+// is the face value of Eq. dbc_lap, so next to the boundary the stencil is the 2SHOC
+// combination, as Sec. 2.1 shows it is inside); and the second-order
 // central difference (CD) D^x + D^y.  Both read only what the 2SHOC tile already
 // holds (two halo rows in registers, two halo columns in LDS).
 #include "tile2d.h"

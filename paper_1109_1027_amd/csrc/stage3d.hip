@@ -29,8 +29,9 @@
 //
 // Alternative Laplacians for comparison (ST, from StageArgs::stencil): the
 // non-compact fourth-order 13-point cross (Sec. 2.3: the 3D counterpart of
-// Eq. 2dnonhoc), one five-point difference per axis with odd-reflection ghosts
-// 2 Psi_b - Psi_{b+-1} one node beyond the boundary, read from the same plane
+// Eq. 2dnonhoc), one five-point difference per axis with the ghosts
+// 2 Psi_b - Psi_{b+-1} + h^2 D^a_b one node beyond a face (their second difference at b is
+// the face value of Eq. dbc_lap), read from the same plane
 // buffer (two-node halo) and column queue (z-2..z+2); and the second-order
 // central difference D^x + D^y + D^z.  Neither needs the D halos in LDS.
 #include "kernels.h"
@@ -172,13 +173,16 @@ __global__ __launch_bounds__(64 * TYB) void stage3d_kernel(StageArgs A, int tile
             const C<R> u = q[2];
             const R i12h2 = (R)(A.c.ih2 / 12.0);
             const C<R> xm1 = sp[ty + 2][tx + 1], xp1 = sp[ty + 2][tx + 3];
-            const C<R> xm2 = x == 1 ? ghost<R>(xm1, u) : sp[ty + 2][tx];
-            const C<R> xp2 = x == nx - 1 ? ghost<R>(xp1, u) : sp[ty + 2][tx + 4];
             const C<R> ym1 = sp[ty + 1][tx + 2], yp1 = sp[ty + 3][tx + 2];
-            const C<R> ym2 = y == 1 ? ghost<R>(ym1, u) : sp[ty][tx + 2];
-            const C<R> yp2 = y == ny - 1 ? ghost<R>(yp1, u) : sp[ty + 4][tx + 2];
-            const C<R> zm2 = z == 1 ? ghost<R>(q[1], u) : q[0];
-            const C<R> zp2 = z == nz - 1 ? ghost<R>(q[3], u) : q[4];
+            // beyond a face: the ghost carrying the face value D^a_b (h^2-scaled)
+            const C<R> xm2 = x == 1 ? ghost<R>(xm1, u, unscaled<R>(DBx[z * (ny + 1) + y], lc.h2)) : sp[ty + 2][tx];
+            const C<R> xp2 = x == nx - 1 ? ghost<R>(xp1, u, unscaled<R>(DBx[fx + z * (ny + 1) + y], lc.h2))
+                                         : sp[ty + 2][tx + 4];
+            const C<R> ym2 = y == 1 ? ghost<R>(ym1, u, unscaled<R>(DBy[z * (nx + 1) + x], lc.h2)) : sp[ty][tx + 2];
+            const C<R> yp2 = y == ny - 1 ? ghost<R>(yp1, u, unscaled<R>(DBy[fy + z * (nx + 1) + x], lc.h2))
+                                         : sp[ty + 4][tx + 2];
+            const C<R> zm2 = z == 1 ? ghost<R>(q[1], u, unscaled<R>(DBz[y * (nx + 1) + x], lc.h2)) : q[0];
+            const C<R> zp2 = z == nz - 1 ? ghost<R>(q[3], u, unscaled<R>(DBz[fz + y * (nx + 1) + x], lc.h2)) : q[4];
             lapnc = cadd<R>(cadd<R>(d4nc<R>(xm2, xm1, u, xp1, xp2, i12h2), d4nc<R>(ym2, ym1, u, yp1, yp2, i12h2)),
                             d4nc<R>(zm2, q[1], u, q[3], zp2, i12h2));
         }

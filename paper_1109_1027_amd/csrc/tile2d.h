@@ -16,7 +16,8 @@ template <typename T> struct same_t<T, T> { static constexpr bool v = true; };
 constexpr int TILE_W = 64;
 
 // ST selects the Laplacian: 0 the per-axis 2SHOC form, 1 the non-compact fourth-order
-// stencil (odd-reflection ghosts one node beyond the boundary), 2 the second-order CD.
+// stencil (one node beyond a face the ghost 2 Psi_b - Psi_{b-+1} + h^2 D^a_b, whose second
+// difference at b is the face value), 2 the second-order CD.
 template <typename IN, typename R, typename M, int RW, int NW, int ST = 0>
 __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, int64_t tiles_x, int64_t tiles_total,
                                              C<R> (*lds)[RW][TILE_W + 4], C<R> (*ldx)[RW][TILE_W + 2])
@@ -132,11 +133,13 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs &A, int64_t tile, i
             const R i12h2 = (R)(A.c.ih2 / 12.0);
             const C<R> c = col[r + 2];
             const C<R> xm1 = lds[wv][r][lane + 1], xp1 = lds[wv][r][lane + 3];
-            const C<R> xm2 = x == 1 ? ghost<R>(xm1, c) : lds[wv][r][lane];
-            const C<R> xp2 = x == L.nx - 1 ? ghost<R>(xp1, c) : lds[wv][r][lane + 4];
             const C<R> ym1 = col[r + 1], yp1 = col[r + 3];
-            const C<R> ym2 = y == 1 ? ghost<R>(ym1, c) : col[r];
-            const C<R> yp2 = y == L.ny - 1 ? ghost<R>(yp1, c) : col[r + 4];
+            // beyond a face: the ghost carrying the face value D^a_b (h^2-scaled)
+            const C<R> xm2 = x == 1 ? ghost<R>(xm1, c, unscaled<R>(DBx[y], lc.h2)) : lds[wv][r][lane];
+            const C<R> xp2 = x == L.nx - 1 ? ghost<R>(xp1, c, unscaled<R>(DBx[(L.ny + 1) + y], lc.h2))
+                                           : lds[wv][r][lane + 4];
+            const C<R> ym2 = y == 1 ? ghost<R>(ym1, c, unscaled<R>(DBy[x], lc.h2)) : col[r];
+            const C<R> yp2 = y == L.ny - 1 ? ghost<R>(yp1, c, unscaled<R>(DBy[(L.nx + 1) + x], lc.h2)) : col[r + 4];
             const C<R> lap = cadd<R>(d4nc<R>(xm2, xm1, c, xp1, xp2, i12h2), d4nc<R>(ym2, ym1, c, yp1, yp2, i12h2));
             F = rhs<R>(lap, u, vv[r], a, s);
         }
