@@ -280,6 +280,25 @@ void nlse_corr_destroy(nlse_corr *m);
 int nlse_inject(const void *src, int32_t src_prec, int64_t src_n, void *dst, int64_t dst_n, int32_t factor,
                 void *stream);
 
+/* ---------------------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops that forbid hipMalloc): the mass of nlse_mass, h^ndim * sum over every node of
+ * |Psi|^2 reduced in FP64 in the same fixed order (bitwise equal to nlse_mass of a context
+ * holding the same field), for a caller's field.  Allocates nothing: the reduction's
+ * partial sums live in a static device array of the library (1024 doubles per GPU, held
+ * until the process ends; its size does not depend on the field, so every field size is
+ * accepted).
+ *   psi:    device pointer, dense [z][y][x] field of (n[a] + 1) nodes per axis a < ndim,
+ *           interleaved complex128 (NLSE_F64, NLSE_F32_MIXED) or complex64 (NLSE_F32).
+ *   out:    device pointer to one double, written by the last kernel of the call.
+ *   stream: hipStream_t the kernels are enqueued on (NULL = default stream); the call
+ *           returns without waiting.
+ * The caller keeps ownership of psi and out.  Calls that overlap on one GPU share the
+ * static array and race: serialise them (one stream, or wait between calls).  Returns
+ * NLSE_E_INVAL for NULL pointers, ndim outside 1..3, n[a] < 1 or h <= 0. */
+int nlse_mass_noalloc(int32_t ndim, const int64_t *n, double h, int32_t prec, const void *psi, double *out,
+                      void *stream);
+
 #ifdef __cplusplus
 }
 #endif

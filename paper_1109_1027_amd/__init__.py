@@ -3,6 +3,6 @@
 The numerical work runs in hand-written HIP kernels behind the C ABI of
 ``include/nlse.h``; ``nlse.Solver`` is a thin ctypes binding of it.
 """
-from .nlse import Batch, Corrector, NLSEError, Solver, inject, load  # noqa: F401
+from .nlse import Batch, Corrector, NLSEError, Solver, inject, load, mass_noalloc  # noqa: F401
 
-__all__ = ["Solver", "Batch", "Corrector", "inject", "NLSEError", "load"]
+__all__ = ["Solver", "Batch", "Corrector", "inject", "NLSEError", "load", "mass_noalloc"]

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(RED_THREADS) void mass_kernel(const C<M> *psi, Layo
 }
 
 hipError_t launch_mass(Prec prec, const void *psin, const Layout &L, double *partials,
-                       double *dev_out, hipStream_t st)
+                       double *dev_out, hipStream_t st, double scale)
 {
     if (prec == P_F32)
         hipLaunchKernelGGL((mass_kernel<float>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st,
@@ -178,7 +178,7 @@ hipError_t launch_mass(Prec prec, const void *psin, const Layout &L, double *par
                            (const C<double> *)psin, L, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(RED_THREADS), 0, st, partials, RED_BLOCKS, 1.0,
+    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(RED_THREADS), 0, st, partials, RED_BLOCKS, scale,
                        dev_out);
     return hipGetLastError();
 }

@@ -114,8 +114,9 @@ hipError_t launch_master_to_stage(Prec prec, const void *psin, void *dst, const 
 // (times 2 for minmax); the result is written to dev_out (device) and is
 // bitwise reproducible for a given layout.
 int reduce_partials();
+// dev_out[0] = scale * (sum of |Psi|^2 over every node).
 hipError_t launch_mass(Prec prec, const void *psin, const Layout &L, double *partials,
-                       double *dev_out, hipStream_t st);
+                       double *dev_out, hipStream_t st, double scale = 1.0);
 hipError_t launch_energy(Prec prec, const void *psin, const void *V, const void *const DB[3],
                          const Layout &L, const Coeffs &c, double *partials, double *dev_out,
                          hipStream_t st);

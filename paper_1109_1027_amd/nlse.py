@@ -45,7 +45,7 @@ EXPORTS = ["nlse_create", "nlse_set_field", "nlse_step", "nlse_get_field", "nlse
            "nlse_corr_param_count", "nlse_corr_create", "nlse_corr_set_params", "nlse_corr_get_params",
            "nlse_corr_infer", "nlse_corr_grads", "nlse_corr_train_step", "nlse_corr_apply",
            "nlse_step_corrected", "nlse_corr_destroy", "nlse_inject", "nlse_corr_set_target_filter",
-           "nlse_corr_set_augment"]
+           "nlse_corr_set_augment", "nlse_mass_noalloc"]
 
 _lib = None
 
@@ -107,6 +107,7 @@ def load():
     L.nlse_inject.argtypes = [vp, i32, i64, vp, i64, i32, vp]
     L.nlse_corr_set_target_filter.argtypes = [vp, i32]
     L.nlse_corr_set_augment.argtypes = [vp, dbl, ctypes.c_uint64]
+    L.nlse_mass_noalloc.argtypes = [i32, ctypes.POINTER(i64), dbl, i32, vp, vp, vp]
     for f in EXPORTS:
         if f not in ("nlse_destroy", "nlse_last_error", "nlse_batch_destroy", "nlse_corr_destroy"):
             getattr(L, f).restype = ctypes.c_int
@@ -469,3 +470,14 @@ def inject(src, src_n, dst, factor, stream="current"):
     st = _current_stream() if stream == "current" else stream
     _check(load().nlse_inject(ctypes.c_void_p(src.data_ptr()), prec, int(src_n), ctypes.c_void_p(dst.data_ptr()),
                               int(src_n) // int(factor), int(factor), st))
+
+
+def mass_noalloc(psi, h, prec, out, stream="current"):
+    """nlse_mass_noalloc: the mass h^ndim sum |Psi|^2 of a dense device field (a torch tensor
+    of (n+1)^ndim complex nodes, complex128 for "f64"/"mixed", complex64 for "f32") into
+    `out`, a one-element float64 device tensor, without any allocation in the library."""
+    ndim = psi.dim()
+    n = (ctypes.c_int64 * 3)(*[int(d) - 1 for d in reversed(psi.shape)], *([0] * (3 - ndim)))
+    st = _current_stream() if stream == "current" else stream
+    _check(load().nlse_mass_noalloc(ndim, n, float(h), PREC[prec], ctypes.c_void_p(psi.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()), st))
