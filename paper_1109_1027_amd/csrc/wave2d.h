@@ -45,9 +45,15 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
 
     const R s = (R)A.c.s;
     const Step2Coef<R> lc = step2_coef<R>(A.c.a, A.c.c76, A.c.c112, A.c.ih2);
-    R ck[4];
+    // The stage updates of stages 1-3 use ck times 1 on interior columns and times 0 elsewhere:
+    // Psi^n + 0 * F is Psi^n exactly, so boundary and outside columns keep their values
+    // (Eq. dbc_ut) without a select (F is finite there: every value those lanes see is a copy
+    // of a field value).  Rows are handled the same way with a wave-uniform factor.
+    R ck[4], ckl[3];
 #pragma unroll
     for (int i = 0; i < 4; ++i) ck[i] = (R)A.ck[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ckl[i] = xint ? ck[i] : R(0);
     const C<M> *__restrict__ pin = (const C<M> *)A.psi_in;
     C<M> *__restrict__ pout = (C<M> *)A.psi_out;
     const R *__restrict__ V = (const R *)A.V;
@@ -112,6 +118,17 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
             }
             load_row(j + PD, pf[PD - 1], vf[PD - 1]);   // prefetch
             const int q0 = p % 3, q1 = (p + 1) % 3, q2 = (p + 2) % 3;   // rows m, m-2, m-1
+            // face values of the four stages' output rows j-2-2st, read before the stages so
+            // that no stage waits for its LDS read (the indices stay inside the staging)
+            C<R> fv[4];
+            if (has_face) {
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const int i = t + HALO - 2 - 2 * st;
+                    if (x == 0) fv[st] = sdx[0][i];
+                    else fv[st] = sdx[1][i];
+                }
+            }
             C<R> in = cvt<R, M>(P[p]);
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
@@ -127,20 +144,17 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                     const int kr = (p + 18 - 2 * (st + 1)) % 9;
                     const C<R> u = U[st][q1];
                     C<R> dx = d2u<R>(clane_prev<R>(u), u, clane_next<R>(u));
-                    if (has_face) {
-                        const C<R> f = sdx[x == 0 ? 0 : 1][r - jb + HALO];
-                        if (xface) dx = f;
-                    }
+                    if (has_face && xface) dx = fv[st];   // fv[st] is row r of the face
                     const C<R> alap = lap2a<R>(dx, D[st][q2], clane_prev<R>(dx), clane_next<R>(dx), D[st][q1], D[st][q0],
                                                lc.A76, lc.A112);
                     const C<R> F = rhs_a<R>(alap, u, Vq[kr], s);
-                    const bool upd = xint && r >= 1 && r < ny;
+                    const bool rowin = r >= 1 && r < ny;   // wave-uniform
                     if (st == 0) {
                         Kq[kr] = F;
-                        outv = upd ? cvt<R, M>(axpy_m<R, M>(P[kr], ck[0], F)) : u;
+                        outv = cvt<R, M>(axpy_m<R, M>(P[kr], rowin ? ckl[0] : R(0), F));
                     } else if (st < 3) {
                         Kq[kr] = kacc<R>(Kq[kr], F);
-                        outv = upd ? cvt<R, M>(axpy_m<R, M>(P[kr], ck[st], F)) : u;
+                        outv = cvt<R, M>(axpy_m<R, M>(P[kr], rowin ? ckl[st] : R(0), F));
                     } else if (wlane && r >= y0 && r < y1) {
                         pout[r * px + x + ox] = axpy_m<R, M>(P[kr], ck[3], cadd<R>(Kq[kr], F));
                     }

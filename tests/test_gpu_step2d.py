@@ -3,8 +3,10 @@
 It performs the same floating-point operations as the four stage launches, so it is checked
 bit for bit against them, and against the FP64 oracle at the parity tolerances (FP64 <= 1e-12,
 FP32 / mixed <= 1e-4 relative L2).  Sizes cover one strip, several 48-column strips and row
-segments with ragged tails, non-square grids, odd step counts (the master buffers swap every
-step) and switches between kernel kinds in the middle of a run.
+segments with ragged tails, grids with inner tasks (no boundary node within a wave's reach,
+the code path without face closures) beside boundary tasks, non-square grids, odd step
+counts (the master buffers swap every step) and switches between kernel kinds in the middle
+of a run.
 """
 import sys
 
@@ -75,7 +77,7 @@ def run(gpu, nx, ny, prec, variant, steps, h, V, psi, dt=None, V_on=True):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
-@pytest.mark.parametrize("nx,ny", [(2, 2), (5, 7), (49, 30), (150, 97), (97, 150), (200, 64)])
+@pytest.mark.parametrize("nx,ny", [(2, 2), (5, 7), (49, 30), (150, 97), (97, 150), (200, 64), (300, 260)])
 def test_whole_step_bitwise_equals_stage_kernels(gpu, prec, nx, ny):
     h, V, psi = gp2d_problem(nx, ny, boundary=True)
     ref, s, dt = run(gpu, nx, ny, prec, 0, 7, h, V, psi)
