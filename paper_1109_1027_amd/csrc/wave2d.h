@@ -9,6 +9,8 @@
 #include "point.h"
 #include "dpp.h"
 
+#include <type_traits>
+
 namespace nlse {
 namespace wave2d {
 
@@ -103,8 +105,10 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
 #pragma unroll
     for (int d = 0; d < PD; ++d) load_row(jb + d, pf[d], vf[d]);
 
-#pragma unroll 1
-    for (int g = 0; g < Q; ++g) {
+    // One group of nine rows.  WARM: the group may hold rows t < 16, where a stage's output is
+    // skipped while its inputs are still filling the pipeline (t < 4 (st + 1)); the first two
+    // groups run with that test, the rest without it.
+    auto group = [&](const int g, auto warm) {
 #pragma unroll
         for (int p = 0; p < 9; ++p) {
             const int t = 9 * g + p;
@@ -139,7 +143,7 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                 if (m - 1 == ny) dy = sdy[1][lane];
                 D[st][q0] = dy;
                 C<R> outv = czero<R>();
-                if (t >= 4 * (st + 1)) {    // earlier output rows feed nothing
+                if (!decltype(warm)::value || t >= 4 * (st + 1)) {    // earlier output rows feed nothing
                     const int r = m - 2;    // output row
                     const int kr = (p + 18 - 2 * (st + 1)) % 9;
                     const C<R> u = U[st][q1];
@@ -148,13 +152,13 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                     const C<R> alap = lap2a<R>(dx, D[st][q2], clane_prev<R>(dx), clane_next<R>(dx), D[st][q1], D[st][q0],
                                                lc.A76, lc.A112);
                     const C<R> F = rhs_a<R>(alap, u, Vq[kr], s);
-                    const bool rowin = r >= 1 && r < ny;   // wave-uniform
+                    const R rowf = (r >= 1 && r < ny) ? R(1) : R(0);   // wave-uniform
                     if (st == 0) {
                         Kq[kr] = F;
-                        outv = cvt<R, M>(axpy_m<R, M>(P[kr], rowin ? ckl[0] : R(0), F));
+                        outv = cvt<R, M>(axpy_m<R, M>(P[kr], ckl[0] * rowf, F));
                     } else if (st < 3) {
                         Kq[kr] = kacc<R>(Kq[kr], F);
-                        outv = cvt<R, M>(axpy_m<R, M>(P[kr], rowin ? ckl[st] : R(0), F));
+                        outv = cvt<R, M>(axpy_m<R, M>(P[kr], ckl[st] * rowf, F));
                     } else if (wlane && r >= y0 && r < y1) {
                         pout[r * px + x + ox] = axpy_m<R, M>(P[kr], ck[3], cadd<R>(Kq[kr], F));
                     }
@@ -162,7 +166,12 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                 in = outv;
             }
         }
-    }
+    };
+    static_assert(Q >= 2, "the first two groups are the warm-up");
+#pragma unroll 1
+    for (int g = 0; g < 2; ++g) group(g, std::true_type{});
+#pragma unroll 1
+    for (int g = 2; g < Q; ++g) group(g, std::false_type{});
 }
 
 }  // namespace wave2d
