@@ -48,6 +48,8 @@ FLOPS_PER_POINT_STEP_1D = 134
 VECTOR_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "mixed": 157.3}
 
 METRIC = "2SHOC-RK4 Gpt·steps/s + % HBM peak; coarse+learned vs plain fine at equal L2 err"
+# timed runs of at most this many steps are checked live against the oracle (cpu_baseline leg)
+LIVE_CHECK_MAX_STEPS = 50
 
 
 def measured_traffic(kind, prec, variant):
@@ -158,12 +160,15 @@ def copy_ceiling_gbs():
     return 10 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
-def cpu_baseline(spec, budget_s=12.0, budget_1core_s=6.0):
+def cpu_baseline(spec, budget_s=12.0, budget_1core_s=6.0, match_steps=None, dt=None):
     """The FP64 oracle on the same grid, a bounded number of RK4 steps on the host cores
-    (all of them, then one)."""
+    (all of them, then one).  With match_steps (at most 50), the all-cores run takes exactly that
+    many steps from the initial field at step dt, the GPU's timed run, and its final field is
+    returned too (the accuracy reference of that run)."""
     import oracle
     P = oracle.Problem.from_spec(spec)
-    dt = 0.5 * P.max_dt(spec.psi0)
+    if dt is None:
+        dt = 0.5 * P.max_dt(spec.psi0)
 
     def run(budget, cap):
         psi, steps, t0 = spec.psi0, 0, time.perf_counter()
@@ -171,16 +176,18 @@ def cpu_baseline(spec, budget_s=12.0, budget_1core_s=6.0):
             psi = P.rk4(psi, 1, dt)
             steps += 1
             el = time.perf_counter() - t0
-            if el >= budget or steps >= cap:
-                return steps, el
+            if (el >= budget and match_steps is None) or steps >= cap:
+                return steps, el, psi
 
     cores = oracle.threads()
-    steps, el = run(budget_s, 50)
+    steps, el, final = run(budget_s, match_steps or 50)
     oracle.set_threads(1)
+    match, match_steps = match_steps, None
     try:
-        steps1, el1 = run(budget_1core_s, 10)
+        steps1, el1, _ = run(budget_1core_s, 10)
     finally:
         oracle.set_threads(cores)
+        match_steps = match
     # the 1D soliton (config 1) is small enough to run whole: its wall time beside the GPU's
     import nlse_inputs as I
     sp1 = I.config_soliton_1d(1024)
@@ -193,12 +200,15 @@ def cpu_baseline(spec, budget_s=12.0, budget_1core_s=6.0):
         el_1d = time.perf_counter() - t0
     finally:
         oracle.set_threads(cores)
-    return {"value": spec.interior_points * steps / el / 1e9, "unit": "Gpt·steps/s",
-            "cores": cores, "kind": "oracle",
-            "sample": f"{steps} RK4 steps of the FP64 oracle on the full {spec.grid.n + 1}^2 grid ({el:.1f} s, {cores} threads); "
-                      f"{steps1} steps on 1 thread ({el1:.1f} s)",
-            "single_core_value": spec.interior_points * steps1 / el1 / 1e9,
-            "soliton1d_full_run_s_1thread": el_1d, "soliton1d_steps": n1}
+    same = " (from the initial field at the GPU's step size: the timed run's accuracy reference)" \
+        if match_steps else ""
+    out = {"value": spec.interior_points * steps / el / 1e9, "unit": "Gpt·steps/s",
+           "cores": cores, "kind": "oracle",
+           "sample": f"{steps} RK4 steps of the FP64 oracle on the full {spec.grid.n + 1}^2 grid{same} ({el:.1f} s, "
+                     f"{cores} threads); {steps1} steps on 1 thread ({el1:.1f} s)",
+           "single_core_value": spec.interior_points * steps1 / el1 / 1e9,
+           "soliton1d_full_run_s_1thread": el_1d, "soliton1d_steps": n1}
+    return (out, final) if match_steps else (out, None)
 
 
 def cpu_baseline_3d(n3d, budget_s=15.0, cap=5):
@@ -373,7 +383,24 @@ def bench_batch(P, I, steps=1000):
     b = P.Batch(specs, prec="f32")
     b.set_fields(specs)
     b.set_dts(0.5)
-    variant = b.autotune(nsteps=5)
+    variant = b.autotune(nsteps=50)
+    # the autotuner's margin: 50 steps of each variant again, best of three (untimed region)
+    tune = {}
+    for v in range(b.variant_count()):
+        b.variant = v
+        b.step(50)   # graph capture for this variant
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(torch.cuda.current_stream())
+            b.step(50)
+            e1.record(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            best = min(best or 1e30, e0.elapsed_time(e1))
+        tune[v] = best
+    b.variant = variant
+    b.set_fields(specs)   # the timed run starts from the initial fields again
     pts1 = sum((sp.grid.n - 1) for sp in specs if sp.dim == 1)
     pts2 = sum((sp.grid.n - 1) ** 2 for sp in specs if sp.dim == 2)
     torch.cuda.synchronize()
@@ -396,6 +423,8 @@ def bench_batch(P, I, steps=1000):
                         "at 256^2 (omega in [0.02, 0.1]), complex64, one persistent graph launch",
             "instances": len(specs), "steps": steps, "interior_point_steps": (pts1 + pts2) * steps,
             "value": gpts, "unit": "Gpt·steps/s", "ms": ms, "tile_variant": variant,
+            "autotune_ms_per_50_steps": tune,
+            "autotune_margin": sorted(tune.values())[1] / sorted(tune.values())[0] - 1.0 if len(tune) > 1 else None,
             "roofline": {"bound": "alu", "achieved": tflops, "peak": VECTOR_PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
                          "frac": tflops / VECTOR_PEAK_TFLOPS["f32"], "traffic": None,
                          "kernel": "nlse::batch2d_kernel + nlse::batch1d_kernel (one graph launch)",
@@ -456,28 +485,25 @@ def bench_msd3d(P, I, args, res3d):
     return out
 
 
-def bench_learned(P, seed=9000):
-    """Coarse (513^2) + learned corrector vs plain runs, all against the 2049^2 plain run at t = 20,
-    on one held-out seed with the committed weights (trained on the GPU by the library's kernels)."""
+def bench_learned(P, seeds=(9000, 9001, 9002, 9003)):
+    """Coarse (513^2) + learned corrector vs plain runs, all against the FP64 2049^2 plain run at
+    t = 20, on the four held-out seeds with the committed weights (trained on the GPU by the
+    library's kernels); mean errors, the worst seed's gain and the equal-error speedup."""
     from paper_1109_1027_amd import corrector as K
     params, scale = K.load_weights()
-    snaps, t_fine = K.fine_trajectory(seed, snapshots=False)
-    R = snaps[-1].cpu().numpy().astype(np.complex128)
-    res = {"seed": seed, "t_fine_s": t_fine, "E": {}, "T": {}}
-    for n in (512, 1024, 1536):
-        out, el, ns = K.plain_run(seed, n)
-        res["E"][n], res["T"][n] = K.rel(out, R), el
-    out, el = K.learned_run(seed, params, scale)
-    res["E_learned"], res["T_learned"] = K.rel(out, R), el
-    summ = K.summarize([res])
-    print(f"[bench] learned: E_plain(513^2) {summ['E_plain'][512]:.3e}, E_learned {summ['E_learned']:.3e}, "
-          f"equal-error speedup {summ['speedup_vs_plain_equal_error']:.2f}x", file=sys.stderr, flush=True)
-    return {"metric": "coarse+learned vs plain at equal L2 error (vs the 2049^2 plain run, t = 20)",
-            "workload": "2D GP, a=0.5 s=-1 omega=0.05, 1-8 vortices + 1e-3 noise, held-out seed; coarse 513^2 "
-                        "with the 3-layer BF16-MFMA conv corrector every 10 steps",
-            **{k: summ[k] for k in ("E_plain", "T_plain_s", "E_learned", "T_learned_s", "T_fine_s", "fit_order_p",
-                                    "n_equal_error", "speedup_vs_plain_equal_error", "speedup_vs_fine",
-                                    "gain_E512_over_learned", "E_fine_run_richardson")}}
+    res = K.evaluate(params, scale, list(seeds))
+    summ = K.summarize(res)
+    print(f"[bench] learned ({len(seeds)} held-out seeds): E_plain(513^2) {summ['E_plain'][512]:.3e}, "
+          f"E_learned {summ['E_learned']:.3e}, mean gain {summ['gain_E512_over_learned']:.2f}x (worst "
+          f"{summ['gain_worst']:.2f}x), equal-error speedup {summ['speedup_vs_plain_equal_error']:.2f}x",
+          file=sys.stderr, flush=True)
+    return {"metric": "coarse+learned vs plain at equal L2 error (vs the FP64 2049^2 plain run, t = 20)",
+            "workload": "2D GP, a=0.5 s=-1 omega=0.05, 1-8 vortices + 1e-3 noise, held-out seeds 9000-9003; "
+                        "coarse 513^2 with the 3-layer BF16-MFMA conv corrector every 10 steps",
+            **{k: summ[k] for k in ("seeds", "E_plain", "T_plain_s", "E_learned", "T_learned_s", "T_fine_s",
+                                    "fit_order_p", "n_equal_error", "speedup_vs_plain_equal_error",
+                                    "speedup_vs_fine", "gain_E512_over_learned", "gain_per_seed", "gain_worst",
+                                    "E_fine_run_richardson")}}
 
 
 def main():
@@ -519,13 +545,21 @@ def main():
     # The full benchmark run (2000 steps at 2049^2) has a stored FP64 oracle state, sampled at 545
     # nodes (tests/golden/gp2d_2048_2000steps.json, written by the oracle alone): each precision's
     # timed run starts from the initial field with the oracle's dt and is compared with it.
-    golden, check = None, None
+    # Other step counts up to 50 (the driver's short run among them) keep their final fields and
+    # are compared over every node with the FP64 oracle's run of the same steps in the
+    # cpu_baseline leg below.
+    golden, check, gold_dt = None, None, None
     gpath = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "gp2d_2048_2000steps.json")
     if os.path.exists(gpath):
         with open(gpath) as f:
             golden = json.load(f)
-        if golden["n"] != args.n or golden["steps"] != args.steps:
+        if golden["n"] != args.n:
             golden = None
+        else:
+            gold_dt = golden["dt"]   # the oracle's step size on this grid (0.5 x its bound)
+            if golden["steps"] != args.steps:
+                golden = None
+    live = golden is None and args.steps <= LIVE_CHECK_MAX_STEPS and not args.no_cpu_baseline
     if golden is not None:
         iy, ix = np.array(golden["nodes"]).T
         gref = np.array(golden["re"]) + 1j * np.array(golden["im"])
@@ -533,11 +567,17 @@ def main():
         def check(field):
             got = np.asarray(field, np.complex128)[iy, ix]
             return float(np.linalg.norm(got - gref) / np.linalg.norm(gref))
+    elif live:
+        def check(field):
+            return np.array(field, np.complex128)
+    finals = {}
     for prec in precs:
         timed = time_solver(P, spec, prec, args.steps, args.warmup, variant=force2d.get(prec),
-                            dt=golden["dt"] if golden else None, check=check)
+                            dt=gold_dt, check=check)
         ms, wall, launches, dt, mass, variant = timed[:6]
         err = timed[6] if len(timed) > 6 else None
+        if live:
+            finals[prec], err = err, None
         gpts = npts * args.steps / (ms * 1e-3) / 1e9
         avg_launch_s = ms * 1e-3 / launches
         whole = launches == args.steps
@@ -591,7 +631,7 @@ def main():
               file=sys.stderr, flush=True)
     # Sec. 5's comparison on this hardware: the stage kernels with the 2SHOC, the non-compact
     # fourth-order and the second-order CD Laplacian (same bytes, different operation counts)
-    stencils = {}
+    stencils, stencils_ws = {}, {}
     if not args.no_stencils:
         for prec in ("f64", "f32"):
             if prec not in res:
@@ -606,6 +646,16 @@ def main():
                                                      "hbm_frac": bw / HBM_PEAK_GBS, "tile_variant": sv}
                 print(f"[bench] stencil {st} {prec} (stage kernels): {stencils[prec][st]['value']:.2f} Gpt*steps/s, "
                       f"{100 * bw / HBM_PEAK_GBS:.1f}% of HBM peak", file=sys.stderr, flush=True)
+            # the same comparison in the whole-step kernel (one launch per step, vector-ALU bound),
+            # where the stencils' operation counts show; variant chosen by the autotuner per stencil
+            for st in ("2shoc", "noncompact", "cd"):
+                steps_w = max(args.steps, 200)
+                ms_w, _, launches_w, _, _, v_w = time_solver(P, spec, prec, steps_w, 10, stencil=st)
+                stencils_ws.setdefault(prec, {})[st] = {
+                    "value": npts * steps_w / (ms_w * 1e-3) / 1e9, "ms_per_step": ms_w / steps_w,
+                    "launches_per_step": launches_w // steps_w, "tile_variant": v_w}
+                print(f"[bench] stencil {st} {prec} (whole-step kernel): "
+                      f"{stencils_ws[prec][st]['value']:.2f} Gpt*steps/s", file=sys.stderr, flush=True)
     main_prec = precs[0]
     out = {
         "metric": METRIC, "value": res[main_prec]["value"], "unit": "Gpt·steps/s", "n_gpus": 1,
@@ -632,6 +682,8 @@ def main():
         print(f"[bench] copy ceiling failed: {e}", file=sys.stderr)
     if stencils:
         out["stencils_stage_kernels"] = stencils
+    if stencils_ws:
+        out["stencils_whole_step"] = stencils_ws
     if not args.no_msd:
         out["msd2d"] = bench_msd(P, I, args, res, npts)
     out["soliton1d"] = bench_1d(P, I)
@@ -645,7 +697,18 @@ def main():
         out["learned"] = bench_learned(P)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(spec)
+        out["cpu_baseline"], ref = cpu_baseline(spec, match_steps=args.steps if live else None,
+                                                dt=res[main_prec]["dt"] if live else None)
+        if ref is not None:   # accuracy of each timed run: every node against the oracle's same steps
+            for prec, f in finals.items():
+                e = float(np.linalg.norm((f - ref).ravel()) / np.linalg.norm(ref.ravel()))
+                tgt = out if prec == main_prec else out["variants"][prec]
+                tgt["rel_l2_vs_fp64_oracle"] = e
+                if prec == main_prec:
+                    out["accuracy_check"] = (f"relative L2 over all {ref.size} nodes against the FP64 oracle's run "
+                                             f"of the same {args.steps} steps from the same initial field and dt")
+                print(f"[bench] {prec}: rel L2 vs FP64 oracle after the timed {args.steps} steps {e:.2e}",
+                      file=sys.stderr, flush=True)
         if args.n3d > 0:
             out["cpu_baseline"]["gp3d"] = cpu_baseline_3d(args.n3d)
         if args.batch_steps > 0:

@@ -172,10 +172,10 @@ int nlse_get_variant(const nlse_ctx *c);
 /* Laplacian of the right-hand side (Dirichlet boundaries; NLSE_E_UNSUPPORTED for the
  * alternatives under MSD, NLSE_E_INVAL for an unknown value).  The non-compact stencil
  * is one five-point difference per axis: the 1D stencil of Sec. 2.1, the 9-point cross of
- * Eq. 2dnonhoc in 2D, the 13-point cross in 3D (Sec. 2.3).  In 2D and 3D the
- * alternatives run in the stage kernels only, so the whole-step and two-stage variants
- * disappear from the variant list while they are selected (such a variant then reverts
- * to variant 0); the 1D on-chip solver runs them in every variant.
+ * Eq. 2dnonhoc in 2D, the 13-point cross in 3D (Sec. 2.3).  In 2D every variant runs them
+ * (stage and whole-step kernels); in 3D they run in the stage kernels only, so the
+ * two-stage variants disappear from the variant list while they are selected (such a
+ * variant then reverts to variant 0); the 1D on-chip solver runs them in every variant.
  * nlse_max_dt keeps the 2SHOC bound of Eq. kdfull (the non-compact stencil has the
  * same spectral radius, CD a smaller one), and nlse_energy always uses the 2SHOC
  * Laplacian.  For the comparisons of Sec. 5 on this hardware. */
@@ -217,9 +217,10 @@ int nlse_batch_mass(nlse_batch *b, int32_t i, double *out);
 int nlse_batch_step(nlse_batch *b, int64_t nsteps);
 int nlse_batch_sync(nlse_batch *b);
 /* Variants of the 2D instances (row segments of 56, 29 or 20 rows for the whole-step wave
- * body) and the autotuner that times nsteps of each, restoring the state.  A 1D instance
- * always runs the on-chip solver body with the smallest node bound per thread that holds
- * it. */
+ * body) and the autotuner: per variant one untimed call of nsteps (graph capture and first
+ * launch), then the fastest of three timed launches of that graph; the state is restored
+ * after every call.  A 1D instance always runs the on-chip solver body with the smallest
+ * node bound per thread that holds it. */
 int nlse_batch_variant_count(const nlse_batch *b);
 int nlse_batch_set_variant(nlse_batch *b, int variant);
 int nlse_batch_get_variant(const nlse_batch *b);
@@ -267,6 +268,26 @@ int nlse_corr_set_target_filter(nlse_corr *m, int32_t smooth);
  * seed and the Adam step, so a training run is reproducible.  sigma = 0 disables it.
  * Inference (nlse_corr_infer / apply / step_corrected) never adds noise. */
 int nlse_corr_set_augment(nlse_corr *m, double sigma, uint64_t seed);
+/* Validation access to the training passes, layer by layer (tests compare each stage with a
+ * CPU reference on the same inputs).  nlse_corr_tensor copies `bytes` bytes between a host
+ * array and an internal tensor (to_device != 0: host -> tensor; waits for the stream).
+ * Layouts are NHWC over the batch's pixels P = batch x H x W: X0 bf16 [P][8] (the features),
+ * A1 / A2 bf16 [P][32], Z1 / Z2 FP32 [P][32] (pre-activations), Y FP32 [P][2], dY bf16 [P][8]
+ * (channels 0-1 used), dZ2 / dZ1 bf16 [P][32], GRADS FP32 in the parameter vector's layout;
+ * bf16 values are raw 16-bit patterns.  nlse_corr_stage runs one stage on them:
+ *   FWD1: Z1 = conv(X0, W1) + b1, A1 = bf16(silu(Z1));  FWD2: the same from A1 to Z2, A2;
+ *   FWD3: Y = conv(A2, W3) + b3;
+ *   WGRAD3 / WGRAD2 / WGRAD1: gradients of W3, b3 (from A2, dY), W2, b2 (A1, dZ2), W1, b1
+ *   (X0, dZ1) into GRADS;  BWD3: dZ2 = bf16(conv^T(dY, W3) silu'(Z2));
+ *   BWD2: dZ1 = bf16(conv^T(dZ2, W2) silu'(Z1)).
+ * Weights are the current parameters rounded to bf16.  NLSE_E_INVAL for an unknown tensor or
+ * stage, more bytes than a tensor holds, or batch outside 1..max_batch. */
+enum { NLSE_CORR_X0 = 0, NLSE_CORR_A1 = 1, NLSE_CORR_A2 = 2, NLSE_CORR_Z1 = 3, NLSE_CORR_Z2 = 4, NLSE_CORR_Y = 5,
+       NLSE_CORR_DY = 6, NLSE_CORR_DZ2 = 7, NLSE_CORR_DZ1 = 8, NLSE_CORR_GRADS = 9 };
+enum { NLSE_CORR_FWD1 = 1, NLSE_CORR_FWD2 = 2, NLSE_CORR_FWD3 = 3, NLSE_CORR_WGRAD3 = 4, NLSE_CORR_BWD3 = 5,
+       NLSE_CORR_WGRAD2 = 6, NLSE_CORR_BWD2 = 7, NLSE_CORR_WGRAD1 = 8 };
+int nlse_corr_tensor(nlse_corr *m, int32_t which, int32_t to_device, void *host, int64_t bytes);
+int nlse_corr_stage(nlse_corr *m, int32_t op, int32_t batch);
 /* One correction of a 2D context's current field (its grid must be H x W nodes and its
  * stream the corrector's). */
 int nlse_corr_apply(nlse_corr *m, nlse_ctx *c);

@@ -73,17 +73,19 @@ def _tuned(s):
     return s
 
 
-def fine_trajectory(seed, snapshots=True, noise=1e-3):
-    """Run the fine problem of `seed` to T_END; return the injected coarse snapshots
-    [N_COARSE_STEPS/EVERY + 1, 513, 513] (complex64, on the GPU) and the run time."""
+def fine_trajectory(seed, snapshots=True, noise=1e-3, prec="f32"):
+    """Run the fine problem of `seed` to T_END in precision `prec`; return the injected coarse
+    snapshots [N_COARSE_STEPS/EVERY + 1, 513, 513] (complex64, on the GPU) and the run time.
+    Training data use FP32 fine runs; the evaluation's reference run is FP64."""
     import torch
     g, psi, V = fine_problem(seed, noise=noise)
-    s = _solver(N_FINE, V)
-    s.set_field(psi.astype(np.complex64))
+    s = _solver(N_FINE, V, prec)
+    s.set_field(psi.astype(s.dtype))
     _tuned(s)
     nc = N_FINE // FACTOR + 1
     nsnap = N_COARSE_STEPS // EVERY
-    buf = torch.empty((N_FINE + 1, N_FINE + 1), dtype=torch.complex64, device="cuda")
+    buf = torch.empty((N_FINE + 1, N_FINE + 1), dtype=torch.complex64 if prec == "f32" else torch.complex128,
+                      device="cuda")
     snaps = torch.empty((nsnap + 1, nc, nc), dtype=torch.complex64, device="cuda")
     chunk = EVERY * FACTOR * FACTOR
     torch.cuda.synchronize()
@@ -113,6 +115,36 @@ def make_pairs(snaps, V):
     torch.cuda.synchronize()
     s.close()
     return pred, snaps[1:]
+
+
+def rollout_pairs(seed, params, scale, V, windows, noise=1e-3):
+    """On-policy pairs: the corrected coarse run of `seed` itself (10 coarse steps, correction,
+    as in learned_run), paired window by window with the injected fine state at the window's
+    end.  pred = the coarse state after the window's 10 steps (before its correction), ref =
+    inject(fine) at that time; `windows` seeded-random windows are kept (all if 0)."""
+    import torch
+    snaps, el = fine_trajectory(seed, noise=noise)
+    nc = snaps.shape[-1]
+    nwin = snaps.shape[0] - 1
+    keep = np.arange(nwin) if not (0 < windows < nwin) else np.sort(
+        np.random.default_rng(seed + 7).choice(nwin, windows, replace=False))
+    s = _solver(nc - 1, V)
+    m = N.Corrector(nc, nc, max_batch=1, V=V)
+    m.set_params(params, scale)
+    s.set_field(snaps[0])
+    pred = torch.empty((len(keep), nc, nc), dtype=torch.complex64, device="cuda")
+    slot = {int(j): k for k, j in enumerate(keep)}
+    for j in range(nwin):
+        s.step(EVERY, DT_C)
+        if j in slot:
+            s.get_field(pred[slot[j]])
+        m.apply(s)
+    torch.cuda.synchronize()
+    ref = snaps[torch.as_tensor(keep + 1, device=snaps.device)].clone()
+    s.close()
+    m.close()
+    del snaps
+    return (pred, ref), el
 
 
 def residual_scale(pairs):
@@ -224,7 +256,7 @@ def rel(a, b):
 def evaluate(params, scale, seeds, sizes=(512, 1024, 1536), damping=(1.0,), noise=1e-3):
     res = []
     for sd in seeds:
-        snaps, t_fine = fine_trajectory(sd, snapshots=False, noise=noise)
+        snaps, t_fine = fine_trajectory(sd, snapshots=False, noise=noise, prec="f64")
         R = snaps[-1].cpu().numpy().astype(np.complex128)
         row = {"seed": sd, "t_fine_s": t_fine, "E": {}, "T": {}}
         for n in sizes:
@@ -259,7 +291,9 @@ def summarize(res, sizes=(512, 1024, 1536)):
     # because the Thomas-Fermi kink limits convergence)
     n_half = N_FINE // 2
     e_ref = E[n_half] * 2.0 ** (-p) / (1.0 - 2.0 ** (-p)) if n_half in E else float("nan")
+    gains = [r["E"][sizes[0]] / r["E_learned"] for r in res]
     return {"E_plain": E, "T_plain_s": T, "E_learned": El, "T_learned_s": Tl, "T_fine_s": Tf,
+            "seeds": [r["seed"] for r in res], "gain_per_seed": gains, "gain_worst": float(min(gains)),
             "fit_order_p": float(p), "n_equal_error": n_star, "T_plain_at_equal_error_s": t_star,
             "speedup_vs_plain_equal_error": t_star / Tl, "speedup_vs_fine": Tf / Tl,
             "gain_E512_over_learned": E[sizes[0]] / El, "E_fine_run_richardson": float(e_ref)}
@@ -279,6 +313,10 @@ def main():
     ap.add_argument("--windows", type=int, default=80,
                     help="keep this many seeded-random 10-step windows per training trajectory (0: all 315)")
     ap.add_argument("--damping", default="1.0,0.7,0.5", help="correction scales tried on the validation seeds")
+    ap.add_argument("--rollout-rounds", type=int, default=0,
+                    help="rounds of on-policy fine-tuning: pairs from the corrected coarse run itself")
+    ap.add_argument("--rollout-steps", type=int, default=4000, help="Adam steps per rollout round")
+    ap.add_argument("--init", default=None, help="start from these weights (skips the first training)")
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--report", default=None)
     args = ap.parse_args()
@@ -286,7 +324,7 @@ def main():
     train_seeds, val_seeds, test_seeds = rng_of(args.train_seeds), rng_of(args.val_seeds), rng_of(args.test_seeds)
     Vc = coarse_potential()
     pairs, t_data = [], 0.0
-    for sd in train_seeds:
+    for sd in (train_seeds if args.init is None else []):
         snaps, el = fine_trajectory(sd, noise=args.train_noise)
         pred, ref = make_pairs(snaps, Vc)
         if 0 < args.windows < pred.shape[0]:   # a seeded subset keeps 200 trajectories within HBM
@@ -299,10 +337,27 @@ def main():
         t_data += el
         log(f"[data] seed {sd}: fine run {el:.2f}s, {pairs[-1][0].shape[0]} pairs")
     t0 = time.perf_counter()
-    params, scale, losses = train(pairs, Vc, steps=args.steps, lr=args.lr, batch=args.batch, smooth=args.smooth,
-                                  augment=args.augment)
+    if args.init is None:
+        params, scale, losses = train(pairs, Vc, steps=args.steps, lr=args.lr, batch=args.batch, smooth=args.smooth,
+                                      augment=args.augment)
+    else:
+        params, scale = load_weights(args.init)
+        losses = [float("nan")]
     t_train = time.perf_counter() - t0
     del pairs
+    # on-policy rounds: the corrected run's own states as inputs, the fine run as the target
+    for rnd in range(args.rollout_rounds):
+        rp = []
+        for sd in train_seeds:
+            pr, el = rollout_pairs(sd, params, scale, Vc, args.windows, noise=args.train_noise)
+            rp.append(pr)
+            t_data += el
+        log(f"[rollout] round {rnd}: {sum(p[0].shape[0] for p in rp)} on-policy pairs")
+        t0 = time.perf_counter()
+        params, _, losses = train(rp, Vc, steps=args.rollout_steps, lr=args.lr * 0.25, batch=args.batch,
+                                  smooth=args.smooth, augment=args.augment, scale=scale, init=params, seed=rnd + 1)
+        t_train += time.perf_counter() - t0
+        del rp
     # the correction scale is chosen on validation seeds, never on the test seeds
     damp = tuple(float(v) for v in args.damping.split(","))
     val = evaluate(params, scale, val_seeds, damping=damp)
@@ -319,7 +374,7 @@ def main():
                  "train_steps": args.steps, "smooth": args.smooth, "damping": alpha, "val_E_by_damping": mean_val,
                  "t_data_s": t_data, "t_train_s": t_train, "loss_first": losses[0],
                  "loss_last100": float(np.mean(losses[-100:])), "scale": scale * alpha,
-                 "train_noise": args.train_noise})
+                 "train_noise": args.train_noise, "rollout_rounds": args.rollout_rounds, "init": args.init})
     log(json.dumps(summ, indent=1, default=float))
     if args.report:
         json.dump({"summary": summ, "per_seed": res, "validation": val}, open(args.report, "w"), indent=1,

@@ -92,6 +92,78 @@ hipError_t launch_boundary_d(Prec prec, const void *psin, const void *V, const L
     }
 }
 
+// ------------------------------------------------- 1D boundary closure ----
+//
+// For both ends b of a 1D field (node 0, node n) the step-1 boundary value D_b from the master
+// field in FP64 -- Eq. dbc_lap (Dirichlet) or Eq. msdbc_lap (MSD: D_b = [Re(D_{b-1}/Psi_{b-1})
+// + (N_{b-1} - N_b)/a] Psi_b with N = s|Psi|^2 - V, the ratio dropped when Psi_{b-1} = 0) -- into
+// DB[side] (stage precision), and under MSD the step-size bound's boundary term
+// max over the ends of (h^2/a) |F_{b-1} / Psi_{b-1}| into *bound_out, with F_{b-1} the
+// right-hand side at b-1 from the 2SHOC combination that uses D_b.  One thread per end.
+template <typename R, typename M>
+__global__ void edges1d_kernel(const C<M> *psi, const R *V, Layout L, Coeffs c, int msd, double h2a, C<R> *DB,
+                               double *bound_out)
+{
+    __shared__ double term[2];
+    const int side = threadIdx.x;
+    if (side < 2) {
+        const int64_t n = L.nx;
+        auto node = [&](int k) { return side ? n - k : (int64_t)k; };   // k-th node inward from the end
+        auto u = [&](int k) {
+            const C<M> v = psi[L.ox + node(k)];
+            return make_double2((double)v.x, (double)v.y);
+        };
+        auto Vq = [&](int k) { return V ? (double)V[L.ox + node(k)] : 0.0; };
+        auto N = [&](int k) {
+            const double2 w = u(k);
+            return c.s * (w.x * w.x + w.y * w.y) - Vq(k);
+        };
+        const double2 ub = u(0);
+        double2 db;
+        double t = 0.0;
+        if (!msd) {
+            const double f = -N(0) / c.a;
+            db = make_double2(f * ub.x, f * ub.y);
+        } else {
+            auto d2 = [&](int k) {   // second difference at node k inward (neighbours k-1, k+1)
+                const double2 lo = u(k - 1), m = u(k), hi = u(k + 1);
+                return make_double2(c.ih2 * ((lo.x - 2.0 * m.x) + hi.x), c.ih2 * ((lo.y - 2.0 * m.y) + hi.y));
+            };
+            const double2 u1 = u(1), D1 = d2(1), D2 = d2(2);
+            const double den = u1.x * u1.x + u1.y * u1.y;
+            const double ratio = den != 0.0 ? (D1.x * u1.x + D1.y * u1.y) / den : 0.0;
+            const double f = ratio + (N(1) - N(0)) / c.a;
+            db = make_double2(f * ub.x, f * ub.y);
+            const double lx = c.c76 * D1.x - (D2.x + db.x) * c.c112, ly = c.c76 * D1.y - (D2.y + db.y) * c.c112;
+            const double zx = c.a * lx + N(1) * u1.x, zy = c.a * ly + N(1) * u1.y;   // F_{b-1} = i z
+            if (den != 0.0) t = h2a * sqrt((zx * zx + zy * zy) / den);
+        }
+        DB[side] = cvt<R, double>(db);
+        term[side] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && bound_out) *bound_out = fmax(term[0], term[1]);
+}
+
+hipError_t launch_edges1d(Prec prec, const void *psin, const void *V, const Layout &L, const Coeffs &c, bool msd,
+                          double h2a, void *DB, double *bound_out, hipStream_t st)
+{
+    switch (prec) {
+    case P_F64:
+        hipLaunchKernelGGL((edges1d_kernel<double, double>), dim3(1), dim3(64), 0, st, (const C<double> *)psin,
+                           (const double *)V, L, c, (int)msd, h2a, (C<double> *)DB, bound_out);
+        break;
+    case P_F32:
+        hipLaunchKernelGGL((edges1d_kernel<float, float>), dim3(1), dim3(64), 0, st, (const C<float> *)psin,
+                           (const float *)V, L, c, (int)msd, h2a, (C<float> *)DB, bound_out);
+        break;
+    default:
+        hipLaunchKernelGGL((edges1d_kernel<float, double>), dim3(1), dim3(64), 0, st, (const C<double> *)psin,
+                           (const float *)V, L, c, (int)msd, h2a, (C<float> *)DB, bound_out);
+    }
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------ master -> stage ----
 
 template <typename R, typename M>

@@ -831,6 +831,73 @@ int nlse_corr_train_step(nlse_corr *m, const void *pred, const void *ref, int32_
     return pack_all(m);
 }
 
+// Internal tensors of the training passes, for validation (see nlse.h).
+int nlse_corr_tensor(nlse_corr *m, int32_t which, int32_t to_device, void *host, int64_t bytes)
+{
+    if (!m || !host || bytes < 0) return fail(NLSE_E_INVAL, "nlse_corr_tensor: bad arguments");
+    const int64_t P = (int64_t)m->maxB * m->H * m->W;
+    void *buf = nullptr;
+    int64_t cap = 0;
+    switch (which) {
+    case NLSE_CORR_X0: buf = m->X0; cap = P * 16; break;
+    case NLSE_CORR_A1: buf = m->A1; cap = P * 64; break;
+    case NLSE_CORR_A2: buf = m->A2; cap = P * 64; break;
+    case NLSE_CORR_Z1: buf = m->Z1; cap = P * 128; break;
+    case NLSE_CORR_Z2: buf = m->Z2; cap = P * 128; break;
+    case NLSE_CORR_Y: buf = m->Y; cap = P * 8; break;
+    case NLSE_CORR_DY: buf = m->dY; cap = P * 16; break;
+    case NLSE_CORR_DZ2: buf = m->dZ2; cap = P * 64; break;
+    case NLSE_CORR_DZ1: buf = m->dZ1; cap = P * 64; break;
+    case NLSE_CORR_GRADS: buf = m->grads; cap = NPARAM * 4; break;
+    default: return fail(NLSE_E_INVAL, "nlse_corr_tensor: unknown tensor");
+    }
+    if (bytes > cap) return fail(NLSE_E_INVAL, "nlse_corr_tensor: more bytes than the tensor holds");
+    HIPTRY(hipMemcpyAsync(to_device ? buf : host, to_device ? host : buf, (size_t)bytes,
+                          to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost, m->stream));
+    HIPTRY(hipStreamSynchronize(m->stream));
+    return NLSE_OK;
+}
+
+// One stage of the training passes on the internal tensors (see nlse.h).
+int nlse_corr_stage(nlse_corr *m, int32_t op, int32_t batch)
+{
+    if (!m || batch < 1 || batch > m->maxB) return fail(NLSE_E_INVAL, "nlse_corr_stage: bad arguments");
+    if (!m->packed) {
+        const int rc = pack_all(m);
+        if (rc) return rc;
+    }
+    const int B = batch, H = m->H, W = m->W;
+    const unsigned g = (unsigned)conv_blocks(B, H, W);
+    switch (op) {
+    case NLSE_CORR_FWD1:
+        hipLaunchKernelGGL((conv_kernel<CORR_CIN, 0>), dim3(g), dim3(256), 0, m->stream, m->X0, (const bf16x8 *)m->pk1,
+                           m->params + OFF_B1, B, H, W, m->Z1, m->A1, nullptr, nullptr, 1);
+        break;
+    case NLSE_CORR_FWD2:
+        hipLaunchKernelGGL((conv_kernel<32, 0>), dim3(g), dim3(256), 0, m->stream, m->A1, (const bf16x8 *)m->pk2,
+                           m->params + OFF_B2, B, H, W, m->Z2, m->A2, nullptr, nullptr, 1);
+        break;
+    case NLSE_CORR_FWD3:
+        hipLaunchKernelGGL((conv_kernel<32, 1>), dim3(g), dim3(256), 0, m->stream, m->A2, (const bf16x8 *)m->pk3,
+                           m->params + OFF_B3, B, H, W, nullptr, nullptr, nullptr, m->Y, 1);
+        break;
+    case NLSE_CORR_WGRAD3: return wgrad<32, 8>(m, m->A2, m->dY, B, m->grads + OFF_W3, m->grads + OFF_B3, CORR_OUT);
+    case NLSE_CORR_BWD3:
+        hipLaunchKernelGGL((conv_kernel<8, 2>), dim3(g), dim3(256), 0, m->stream, m->dY, (const bf16x8 *)m->pk3t,
+                           nullptr, B, H, W, nullptr, m->dZ2, m->Z2, nullptr, -1);
+        break;
+    case NLSE_CORR_WGRAD2: return wgrad<32, 32>(m, m->A1, m->dZ2, B, m->grads + OFF_W2, m->grads + OFF_B2, 32);
+    case NLSE_CORR_BWD2:
+        hipLaunchKernelGGL((conv_kernel<32, 2>), dim3(g), dim3(256), 0, m->stream, m->dZ2, (const bf16x8 *)m->pk2t,
+                           nullptr, B, H, W, nullptr, m->dZ1, m->Z1, nullptr, -1);
+        break;
+    case NLSE_CORR_WGRAD1: return wgrad<CORR_CIN, 32>(m, m->X0, m->dZ1, B, m->grads + OFF_W1, m->grads + OFF_B1, 32);
+    default: return fail(NLSE_E_INVAL, "nlse_corr_stage: unknown stage");
+    }
+    HIPTRY(hipGetLastError());
+    return NLSE_OK;
+}
+
 int nlse_corr_apply(nlse_corr *m, nlse_ctx *c)
 {
     if (!m || !c) return fail(NLSE_E_INVAL, "nlse_corr_apply: NULL argument");

@@ -37,5 +37,4 @@ struct nlse_ctx {
     bool have_field = false;
     int variant = 0;            // kernel variant (tile shape; in 2D also stage vs whole-step kernels)
     int stencil = 0;            // 2D Laplacian: NLSE_STENCIL_* (the whole-step kernels are 2SHOC only)
-    std::vector<double> Vhost;  // for host-side MSD closure (1D)
 };

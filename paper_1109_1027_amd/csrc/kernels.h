@@ -48,6 +48,7 @@ struct Step2DArgs {
     Coeffs c;            // ck unused
     double ck[4];        // k/2, k/2, k, k/6
     int variant;
+    int stencil;         // 0 2SHOC, 1 non-compact fourth order, 2 second-order CD
 };
 hipError_t launch_step2d(Prec prec, const Step2DArgs &a, hipStream_t st);
 int step2d_variants();
@@ -105,6 +106,12 @@ hipError_t launch_msd_faces(Prec prec, bool master, const void *in, const void *
 hipError_t launch_msd_stage(Prec prec, const StageArgs &a, void *const DB[3], hipStream_t st);
 hipError_t launch_msd_bound(Prec prec, const void *psin, const void *V, const void *const DB[3], const Layout &L,
                             const Coeffs &c, double h2a, double *dev_out, hipStream_t st);
+
+// 1D boundary closure on the device (aux.hip): D_b of both ends (Eq. dbc_lap, or Eq. msdbc_lap
+// when msd) into DB ([2] stage complex), and under MSD the bound's boundary term
+// max (h^2/a)|F_{b-1}/Psi_{b-1}| into *bound_out (may be nullptr).
+hipError_t launch_edges1d(Prec prec, const void *psin, const void *V, const Layout &L, const Coeffs &c, bool msd,
+                          double h2a, void *DB, double *bound_out, hipStream_t st);
 
 // Copy the master field into a stage field, converting to the stage type.
 hipError_t launch_master_to_stage(Prec prec, const void *psin, void *dst, const Layout &L,

@@ -128,8 +128,7 @@ __device__ __forceinline__ C<R> face_closure(const Field<IN, R> &f, const Coeffs
     C<R> Dq = czero<R>();   // the full step-1 value at b-1 (Eqs. 2d2shocs1, 3d2shocs)
 #pragma unroll
     for (int t = 0; t < DIM; ++t) Dq = cadd<R>(Dq, f.d2a(q, t, ih2));
-    const R den = uq.x * uq.x + uq.y * uq.y;
-    const R ratio = den != R(0) ? (Dq.x * uq.x + Dq.y * uq.y) / den : R(0);
+    const R ratio = re_div<R>(Dq, uq);
     const R fac = ratio + (nonlin<R>(uq, f.pot(q), s) - nonlin<R>(ub, f.pot(b), s)) * (R)cf.ia;
     C<R> Db = mk<R>(fac * ub.x, fac * ub.y);   // Lap_b
 #pragma unroll
@@ -203,8 +202,7 @@ __device__ C<R> interior_F(const Field<IN, R> &f, const Faces &face_value, const
 template <typename R>
 __device__ __forceinline__ R phase_rate(const C<R> &F, const C<R> &u)
 {
-    const R den = u.x * u.x + u.y * u.y;
-    return den != R(0) ? (F.y * u.x - F.x * u.y) / den : R(0);
+    return im_div<R>(F, u);
 }
 
 // ---- 1. face values D^a_b from the stage input -------------------------------------------

@@ -186,8 +186,7 @@ __device__ void solve1d_onchip(const Solve1DArgs &A, unsigned char *smem_raw)
                     } else {
                         const C<R> ui = b0 ? U[jp] : U[jq], Di = b0 ? D[jp] : D[jq];
                         const R vi = b0 ? Vv[jp] : Vv[jq];
-                        const R den = ui.x * ui.x + ui.y * ui.y;
-                        const R ratio = den != R(0) ? (Di.x * ui.x + Di.y * ui.y) / den : R(0);
+                        const R ratio = re_div<R>(Di, ui);
                         D[j] = cscale<R>(ratio + (nonlin<R>(ui, vi, s) - nonlin<R>(ub, Vv[j], s)) * ia, ub);
                     }
                 }
@@ -200,8 +199,7 @@ __device__ void solve1d_onchip(const Solve1DArgs &A, unsigned char *smem_raw)
                         if (!(b0 || bn) || j >= npt) continue;
                         const int jp = j + 1 < NPT ? j + 1 : j, jq = j > 0 ? j - 1 : 0;   // constants once unrolled
                         const C<R> Fi = b0 ? Fint(jp) : Fint(jq), ui = b0 ? U[jp] : U[jq], ub = U[j];
-                        const R den = ui.x * ui.x + ui.y * ui.y;
-                        const R im = den != R(0) ? (Fi.y * ui.x - Fi.x * ui.y) / den : R(0);
+                        const R im = im_div<R>(Fi, ui);
                         Fb = mk<R>(-im * ub.y, im * ub.x);
                     }
                 }

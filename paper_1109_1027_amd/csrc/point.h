@@ -152,6 +152,35 @@ __device__ __forceinline__ C<R> unscaled(C<R> d, R h2)
     return mk<R>(d.x * h2, d.y * h2);
 }
 
+// Re(D / u) and Im(F / u) for the MSD closure (Sec. 3.2, Eqs. msdbc_lap, msdbc_ut), 0 when
+// u = 0 (the ratio term is then dropped).  Numerator and u are first scaled by 2^-e with
+// max(|u.x|, |u.y|) = f 2^e, 1/2 <= f < 1 (exact), so |u|^2 neither underflows nor loses its
+// low bits when |u| is tiny (in FP32 |u|^2 is subnormal below |u| ~ 1e-19).
+__device__ __forceinline__ float scale2(float v, int e) { return ldexpf(v, e); }
+__device__ __forceinline__ double scale2(double v, int e) { return ldexp(v, e); }
+__device__ __forceinline__ int exponent_of(float v) { int e; (void)frexpf(v, &e); return e; }
+__device__ __forceinline__ int exponent_of(double v) { int e; (void)frexp(v, &e); return e; }
+template <typename R>
+__device__ __forceinline__ R re_div(C<R> D, C<R> u)
+{
+#pragma clang fp contract(off)
+    const R m = fmax(fabs(u.x), fabs(u.y));
+    if (m == R(0)) return R(0);
+    const int e = -exponent_of(m);
+    const R ux = scale2(u.x, e), uy = scale2(u.y, e), dx = scale2(D.x, e), dy = scale2(D.y, e);
+    return (dx * ux + dy * uy) / (ux * ux + uy * uy);
+}
+template <typename R>
+__device__ __forceinline__ R im_div(C<R> F, C<R> u)
+{
+#pragma clang fp contract(off)
+    const R m = fmax(fabs(u.x), fabs(u.y));
+    if (m == R(0)) return R(0);
+    const int e = -exponent_of(m);
+    const R ux = scale2(u.x, e), uy = scale2(u.y, e), fx = scale2(F.x, e), fy = scale2(F.y, e);
+    return (fy * ux - fx * uy) / (ux * ux + uy * uy);
+}
+
 // K_tot accumulation of stages 2 and 3: K + 2F (2F is exact).
 template <typename R>
 __device__ __forceinline__ C<R> kacc(C<R> k, C<R> F)

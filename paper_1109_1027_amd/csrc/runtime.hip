@@ -119,8 +119,7 @@ static hipError_t launch_stage(nlse_ctx *c, int stage, double dt, int variant)
 // whole-step kernels (their 32-bit offsets need fields below 2^31 elements).
 static bool step2d_ok(const nlse_ctx *c)
 {
-    return c->p.ndim == 2 && c->stencil == NLSE_STENCIL_2SHOC && c->p.bc == NLSE_BC_DIRICHLET &&
-           c->L.total < (int64_t(1) << 31);
+    return c->p.ndim == 2 && c->p.bc == NLSE_BC_DIRICHLET && c->L.total < (int64_t(1) << 31);
 }
 
 // 3D variants: [0, stage3d_variants()) the stage kernels, the rest the two-stage pairs
@@ -182,6 +181,7 @@ static hipError_t launch_whole_step(nlse_ctx *c, double dt, int variant)
     a.ck[2] = dt;
     a.ck[3] = dt / 6.0;
     a.variant = variant - stage2d_variants();
+    a.stencil = c->stencil;
     hipError_t e = launch_step2d(c->prec, a, c->stream);
     if (e == hipSuccess) std::swap(c->psi, c->psi2);
     return e;
@@ -248,7 +248,7 @@ int nlse_set_stencil(nlse_ctx *c, int32_t stencil)
     if (stencil != NLSE_STENCIL_2SHOC && c->p.bc != NLSE_BC_DIRICHLET)
         return fail(NLSE_E_UNSUPPORTED, "the alternative stencils are implemented for Dirichlet boundaries only");
     c->stencil = stencil;
-    if (c->variant >= variant_count(c)) c->variant = 0;   // whole-step and two-stage variants are 2SHOC only
+    if (c->variant >= variant_count(c)) c->variant = 0;   // the 3D two-stage variants are 2SHOC only
     return NLSE_OK;
 }
 
@@ -383,7 +383,6 @@ int nlse_create(nlse_ctx **out, const nlse_params *p)
             hipError_t e = hipMemcpy2D((char *)c->V + c->L.ox * c->rR, c->L.px * c->rR, host.data(),
                                        w * c->rR, w * c->rR, rows, hipMemcpyHostToDevice);
             if (e != hipSuccess) rc = hipfail(e, "hipMemcpy2D(V)");
-            if (p->ndim == 1) c->Vhost.assign(p->V, p->V + w);
         }
     }
     if (!rc && p->ndim == 2 && !p->V) rc = alloc(&c->V0, T * c->rR);   // alloc zero-fills
@@ -442,51 +441,6 @@ static int read_scalars(nlse_ctx *c, double *dst, int count)
     return NLSE_OK;
 }
 
-// Nodes 0..3 and n-3..n of a 1D field, converted to complex double on the host.
-static int host_edges_1d(nlse_ctx *c, double out[8][2])
-{
-    const int64_t n = c->L.nx;
-    const int64_t idx[8] = {0, 1, 2, 3, n - 3, n - 2, n - 1, n};
-    for (int k = 0; k < 8; ++k) {
-        unsigned char buf[16];
-        HIPTRY(hipMemcpyAsync(buf, (char *)c->psi + (c->L.ox + idx[k]) * c->esM, c->esM, hipMemcpyDeviceToHost,
-                              c->stream));
-        HIPTRY(hipStreamSynchronize(c->stream));
-        if (c->esM == 16) {
-            out[k][0] = ((double *)buf)[0];
-            out[k][1] = ((double *)buf)[1];
-        } else {
-            out[k][0] = ((float *)buf)[0];
-            out[k][1] = ((float *)buf)[1];
-        }
-    }
-    return NLSE_OK;
-}
-
-// MSD closure values at one end of a 1D field (host, FP64), from nodes b, b-1, b-2, b-3
-// in u[0..3]: returns D_b (Eq. msdbc_lap) and F_{b-1}.
-static void msd_end(const nlse_ctx *c, const double u[4][2], const double Vq[4], double Db[2], double Fbm1[2])
-{
-    const double ih2 = 1.0 / (c->p.h * c->p.h), a = c->p.a, s = c->p.s;
-    auto d2 = [&](int i, double r[2]) {   // second difference at u[i] (neighbours u[i-1], u[i+1])
-        r[0] = ih2 * ((u[i - 1][0] - 2.0 * u[i][0]) + u[i + 1][0]);
-        r[1] = ih2 * ((u[i - 1][1] - 2.0 * u[i][1]) + u[i + 1][1]);
-    };
-    auto N = [&](int i) { return s * (u[i][0] * u[i][0] + u[i][1] * u[i][1]) - Vq[i]; };
-    double D1[2], D2[2];
-    d2(1, D1);
-    d2(2, D2);
-    const double den = u[1][0] * u[1][0] + u[1][1] * u[1][1];
-    const double ratio = den != 0.0 ? (D1[0] * u[1][0] + D1[1] * u[1][1]) / den : 0.0;
-    const double f = ratio + (N(1) - N(0)) / a;
-    Db[0] = f * u[0][0];
-    Db[1] = f * u[0][1];
-    const double lap[2] = {7.0 / 6.0 * D1[0] - (D2[0] + Db[0]) / 12.0, 7.0 / 6.0 * D1[1] - (D2[1] + Db[1]) / 12.0};
-    const double z[2] = {a * lap[0] + N(1) * u[1][0], a * lap[1] + N(1) * u[1][1]};
-    Fbm1[0] = -z[1];
-    Fbm1[1] = z[0];
-}
-
 int nlse_max_dt(nlse_ctx *c, double *out)
 {
     if (!c || !out) return fail(NLSE_E_INVAL, "nlse_max_dt: NULL argument");
@@ -510,22 +464,13 @@ int nlse_max_dt(nlse_ctx *c, double *out)
         rc = read_scalars(c, &B, 1);
         if (rc) return rc;
         m = std::fmax(m, B);
-    } else if (c->p.bc == NLSE_BC_MSD) {
-        double e[8][2];
-        rc = host_edges_1d(c, e);
+    } else if (c->p.bc == NLSE_BC_MSD) {   // 1D: the two ends on the device
+        HIPTRY(launch_edges1d(c->prec, c->psi, c->V, c->L, base_coeffs(c->p), true, h2a, c->DB[0],
+                              c->red + 2 * reduce_partials(), c->stream));
+        double B;
+        rc = read_scalars(c, &B, 1);
         if (rc) return rc;
-        const int64_t n = c->L.nx;
-        auto Vh = [&](int64_t i) { return c->Vhost.empty() ? 0.0 : c->Vhost[(size_t)i]; };
-        const double lo[4][2] = {{e[0][0], e[0][1]}, {e[1][0], e[1][1]}, {e[2][0], e[2][1]}, {e[3][0], e[3][1]}};
-        const double hi[4][2] = {{e[7][0], e[7][1]}, {e[6][0], e[6][1]}, {e[5][0], e[5][1]}, {e[4][0], e[4][1]}};
-        const double vlo[4] = {Vh(0), Vh(1), Vh(2), Vh(3)}, vhi[4] = {Vh(n), Vh(n - 1), Vh(n - 2), Vh(n - 3)};
-        for (int side = 0; side < 2; ++side) {
-            double Db[2], F1[2];
-            const double(*u)[2] = side ? hi : lo;
-            msd_end(c, u, side ? vhi : vlo, Db, F1);
-            const double den = u[1][0] * u[1][0] + u[1][1] * u[1][1];
-            if (den != 0.0) m = std::fmax(m, h2a * std::sqrt((F1[0] * F1[0] + F1[1] * F1[1]) / den));
-        }
+        m = std::fmax(m, B);
     }
     *out = std::sqrt(8.0) * c->p.h * c->p.h / (c->p.a * m);
     return NLSE_OK;
@@ -597,36 +542,9 @@ int nlse_energy(nlse_ctx *c, double *out)
 {
     if (!c || !out) return fail(NLSE_E_INVAL, "nlse_energy: NULL argument");
     Coeffs co = base_coeffs(c->p);
-    if (c->p.ndim == 1) {
-        // boundary closure of the current field (Dirichlet Eq. dbc_lap or MSD Eq. msdbc_lap)
-        double e[8][2];
-        int rc = host_edges_1d(c, e);
-        if (rc) return rc;
-        const int64_t n = c->L.nx;
-        auto Vh = [&](int64_t i) { return c->Vhost.empty() ? 0.0 : c->Vhost[(size_t)i]; };
-        double db[2][2];
-        const int ends[2] = {0, 7};
-        for (int side = 0; side < 2; ++side) {
-            const double *ub = e[ends[side]];
-            if (c->p.bc == NLSE_BC_MSD) {
-                const double lo[4][2] = {{e[0][0], e[0][1]}, {e[1][0], e[1][1]}, {e[2][0], e[2][1]}, {e[3][0], e[3][1]}};
-                const double hi[4][2] = {{e[7][0], e[7][1]}, {e[6][0], e[6][1]}, {e[5][0], e[5][1]}, {e[4][0], e[4][1]}};
-                const double vlo[4] = {Vh(0), Vh(1), Vh(2), Vh(3)}, vhi[4] = {Vh(n), Vh(n - 1), Vh(n - 2), Vh(n - 3)};
-                double F1[2];
-                msd_end(c, side ? hi : lo, side ? vhi : vlo, db[side], F1);
-            } else {
-                const double N = c->p.s * (ub[0] * ub[0] + ub[1] * ub[1]) - Vh(side ? n : 0);
-                db[side][0] = -N * ub[0] / c->p.a;
-                db[side][1] = -N * ub[1] / c->p.a;
-            }
-        }
-        double tmpd[4] = {db[0][0], db[0][1], db[1][0], db[1][1]};
-        float tmpf[4] = {(float)db[0][0], (float)db[0][1], (float)db[1][0], (float)db[1][1]};
-        const void *src = c->esR == 16 ? (const void *)tmpd : (const void *)tmpf;
-        HIPTRY(hipMemcpyAsync(c->DB[0], src, c->esR == 16 ? sizeof tmpd : sizeof tmpf, hipMemcpyHostToDevice,
+    if (c->p.ndim == 1)   // boundary closure of the current field (Eq. dbc_lap or Eq. msdbc_lap)
+        HIPTRY(launch_edges1d(c->prec, c->psi, c->V, c->L, co, c->p.bc == NLSE_BC_MSD, 0.0, c->DB[0], nullptr,
                               c->stream));
-        HIPTRY(hipStreamSynchronize(c->stream));
-    }
     if (c->p.ndim > 1 && c->p.bc == NLSE_BC_MSD)   // face values of the current field (Eq. msdbc_lap)
         HIPTRY(launch_msd_faces(c->prec, true, c->psi, c->V, c->L, co, c->DB, c->stream));
     const void *db[3] = {c->DB[0], c->DB[1], c->DB[2]};

@@ -33,7 +33,7 @@ namespace {
 
 constexpr int NW = 4;      // waves per block (independent)
 
-template <typename R, typename M, int Q, int PD>
+template <typename R, typename M, int Q, int PD, int ST>
 __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs A, int strips, int waves)
 {
     constexpr int FR = wave2d::face_rows<Q>();
@@ -44,10 +44,10 @@ __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs A, int strips, i
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int w = (int)xcd_remap(blockIdx.x, gridDim.x) * NW + wv;
     if (w >= waves) return;                 // whole waves only; the kernel has no barriers
-    wave2d::step2d_wave<R, M, Q, PD>(A, w % strips, w / strips, threadIdx.x & 63, sdx[wv], sdy[wv]);
+    wave2d::step2d_wave<R, M, Q, PD, ST>(A, w % strips, w / strips, threadIdx.x & 63, sdx[wv], sdy[wv]);
 }
 
-template <typename R, typename M, int Q, int PD = 1>
+template <typename R, typename M, int ST, int Q, int PD = 1>
 hipError_t launch_q(const Step2DArgs &a, hipStream_t st)
 {
     if (a.L.total >= (int64_t(1) << 31)) return hipErrorInvalidValue;   // 32-bit offsets
@@ -55,21 +55,32 @@ hipError_t launch_q(const Step2DArgs &a, hipStream_t st)
     const int segs = wave2d::segments<Q>(a.L.ny);
     const int waves = strips * segs;
     const int blocks = (waves + NW - 1) / NW;
-    hipLaunchKernelGGL((step2d_kernel<R, M, Q, PD>), dim3(blocks), dim3(64 * NW), 0, st, a, strips, waves);
+    hipLaunchKernelGGL((step2d_kernel<R, M, Q, PD, ST>), dim3(blocks), dim3(64 * NW), 0, st, a, strips, waves);
     return hipGetLastError();
 }
 
-template <typename R, typename M>
+template <typename R, typename M, int ST>
 hipError_t launch_v(const Step2DArgs &a, hipStream_t st)
 {
     switch (a.variant) {
-    case 0: return launch_q<R, M, 5>(a, st);    // 29-row segments
-    case 1: return launch_q<R, M, 4>(a, st);    // 20
-    case 2: return launch_q<R, M, 6>(a, st);    // 38
-    case 3: return launch_q<R, M, 8>(a, st);    // 56
-    case 4: return launch_q<R, M, 3>(a, st);    // 11 (small grids: more, shorter waves)
-    case 5: return launch_q<R, M, 7>(a, st);    // 47
-    case 6: return launch_q<R, M, 5, 2>(a, st);  // 29, two rows of Psi^n in flight (pays off in mixed)
+    case 0: return launch_q<R, M, ST, 5>(a, st);    // 29-row segments
+    case 1: return launch_q<R, M, ST, 4>(a, st);    // 20
+    case 2: return launch_q<R, M, ST, 6>(a, st);    // 38
+    case 3: return launch_q<R, M, ST, 8>(a, st);    // 56
+    case 4: return launch_q<R, M, ST, 3>(a, st);    // 11 (small grids: more, shorter waves)
+    case 5: return launch_q<R, M, ST, 7>(a, st);    // 47
+    case 6: return launch_q<R, M, ST, 5, 2>(a, st);  // 29, two rows of Psi^n in flight (pays off in mixed)
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R, typename M>
+hipError_t launch_s(const Step2DArgs &a, hipStream_t st)
+{
+    switch (a.stencil) {
+    case 0: return launch_v<R, M, 0>(a, st);
+    case 1: return launch_v<R, M, 1>(a, st);
+    case 2: return launch_v<R, M, 2>(a, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -81,9 +92,9 @@ int step2d_variants() { return 7; }
 hipError_t launch_step2d(Prec prec, const Step2DArgs &a, hipStream_t st)
 {
     switch (prec) {
-    case P_F64: return launch_v<double, double>(a, st);
-    case P_F32: return launch_v<float, float>(a, st);
-    default: return launch_v<float, double>(a, st);
+    case P_F64: return launch_s<double, double>(a, st);
+    case P_F32: return launch_s<float, float>(a, st);
+    default: return launch_s<float, double>(a, st);
     }
 }
 

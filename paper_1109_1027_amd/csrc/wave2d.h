@@ -27,7 +27,10 @@ template <int Q> __host__ __device__ inline int segments(int64_t ny) { return (i
 // rows), sdy: [2][64] (D^y on the faces y = 0 and y = ny for its columns);
 // wave-private LDS, rewritten by every call.  strip < strips(nx) and
 // seg < segments<Q>(ny), wave-uniform; the field has < 2^31 elements.
-template <typename R, typename M, int Q, int PD = 1>
+// ST selects the Laplacian as in the stage kernels: 0 the per-axis 2SHOC form, 1 the
+// non-compact five-point stencil (ghosts 2 Psi_b - Psi_{b-+1} + h^2 D^a_b beyond a face), 2 the
+// second-order CD.
+template <typename R, typename M, int Q, int PD = 1, int ST = 0>
 __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int seg, int lane,
                                             C<R> (*sdx)[face_rows<Q>()], C<R> (*sdy)[64])
 {
@@ -75,8 +78,10 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
     __builtin_amdgcn_wave_barrier();
 
     C<R> U[4][3], D[4][3], Kq[9];
+    C<R> Uq[4][5];   // non-compact stencil: each stage's input rows m-4 .. m (a shift queue)
     C<M> P[9];
     R Vq[9];
+    const R aR = (R)A.c.a, i12h2 = (R)(A.c.ih2 / 12.0), aih2 = (R)(A.c.a * A.c.ih2);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         Kq[i] = czero<R>();
@@ -84,9 +89,12 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
         Vq[i] = R(0);
     }
 #pragma unroll
-    for (int st = 0; st < 4; ++st)
+    for (int st = 0; st < 4; ++st) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) U[st][i] = D[st][i] = czero<R>();
+#pragma unroll
+        for (int i = 0; i < 5; ++i) Uq[st][i] = czero<R>();
+    }
 
     // Row loads are unconditional, with the address clamped into the field: the
     // number of loads in flight never depends on the path, so waiting for a
@@ -129,7 +137,7 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
 #pragma unroll
                 for (int st = 0; st < 4; ++st) {
                     const int i = t + HALO - 2 - 2 * st;
-                    if (x == 0) fv[st] = sdx[0][i];
+                    if (x == (ST == 1 ? 1 : 0)) fv[st] = sdx[0][i];
                     else fv[st] = sdx[1][i];
                 }
             }
@@ -137,21 +145,46 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
                 const int m = j - 2 * st;   // newest input row of this stage
-                U[st][q0] = in;
-                C<R> dy = d2u<R>(U[st][q1], U[st][q2], U[st][q0]);   // h^2 D^y at row m-1
-                if (m - 1 == 0) dy = sdy[0][lane];
-                if (m - 1 == ny) dy = sdy[1][lane];
-                D[st][q0] = dy;
+                if constexpr (ST == 1) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) Uq[st][i] = Uq[st][i + 1];
+                    Uq[st][4] = in;
+                } else {
+                    U[st][q0] = in;
+                    C<R> dy = d2u<R>(U[st][q1], U[st][q2], U[st][q0]);   // h^2 D^y at row m-1
+                    if (m - 1 == 0) dy = sdy[0][lane];
+                    if (m - 1 == ny) dy = sdy[1][lane];
+                    D[st][q0] = dy;
+                }
                 C<R> outv = czero<R>();
                 if (!decltype(warm)::value || t >= 4 * (st + 1)) {    // earlier output rows feed nothing
                     const int r = m - 2;    // output row
                     const int kr = (p + 18 - 2 * (st + 1)) % 9;
-                    const C<R> u = U[st][q1];
-                    C<R> dx = d2u<R>(clane_prev<R>(u), u, clane_next<R>(u));
-                    if (has_face && xface) dx = fv[st];   // fv[st] is row r of the face
-                    const C<R> alap = lap2a<R>(dx, D[st][q2], clane_prev<R>(dx), clane_next<R>(dx), D[st][q1], D[st][q0],
-                                               lc.A76, lc.A112);
-                    const C<R> F = rhs_a<R>(alap, u, Vq[kr], s);
+                    const C<R> u = ST == 1 ? Uq[st][2] : U[st][q1];
+                    C<R> F;
+                    if constexpr (ST == 0) {
+                        C<R> dx = d2u<R>(clane_prev<R>(u), u, clane_next<R>(u));
+                        if (has_face && xface) dx = fv[st];   // fv[st] is row r of the face
+                        const C<R> alap = lap2a<R>(dx, D[st][q2], clane_prev<R>(dx), clane_next<R>(dx), D[st][q1],
+                                                   D[st][q0], lc.A76, lc.A112);
+                        F = rhs_a<R>(alap, u, Vq[kr], s);
+                    } else if constexpr (ST == 2) {   // a/h^2 (D^x + D^y) from the unscaled differences
+                        const C<R> dx = d2u<R>(clane_prev<R>(u), u, clane_next<R>(u));
+                        F = rhs_a<R>(cscale<R>(aih2, cadd<R>(dx, D[st][q2])), u, Vq[kr], s);
+                    } else {   // five-point differences along x (lanes) and y (the row queue)
+                        const C<R> xm1 = clane_prev<R>(u), xp1 = clane_next<R>(u);
+                        C<R> xm2 = clane_prev<R>(xm1), xp2 = clane_next<R>(xp1);
+                        if (has_face) {   // fv[st]: the face value of row r next to lane x = 1 / nx - 1
+                            if (x == 1) xm2 = ghost<R>(xm1, u, fv[st]);
+                            if (x == nx - 1) xp2 = ghost<R>(xp1, u, fv[st]);
+                        }
+                        C<R> ym2 = Uq[st][0], yp2 = Uq[st][4];
+                        if (r == 1) ym2 = ghost<R>(Uq[st][1], u, sdy[0][lane]);
+                        if (r == ny - 1) yp2 = ghost<R>(Uq[st][3], u, sdy[1][lane]);
+                        const C<R> lap = cadd<R>(d4nc<R>(xm2, xm1, u, xp1, xp2, i12h2),
+                                                 d4nc<R>(ym2, Uq[st][1], u, Uq[st][3], yp2, i12h2));
+                        F = rhs<R>(lap, u, Vq[kr], aR, s);
+                    }
                     const R rowf = (r >= 1 && r < ny) ? R(1) : R(0);   // wave-uniform
                     if (st == 0) {
                         Kq[kr] = F;

@@ -45,7 +45,7 @@ EXPORTS = ["nlse_create", "nlse_set_field", "nlse_step", "nlse_get_field", "nlse
            "nlse_corr_param_count", "nlse_corr_create", "nlse_corr_set_params", "nlse_corr_get_params",
            "nlse_corr_infer", "nlse_corr_grads", "nlse_corr_train_step", "nlse_corr_apply",
            "nlse_step_corrected", "nlse_corr_destroy", "nlse_inject", "nlse_corr_set_target_filter",
-           "nlse_corr_set_augment", "nlse_mass_noalloc"]
+           "nlse_corr_set_augment", "nlse_mass_noalloc", "nlse_corr_tensor", "nlse_corr_stage"]
 
 _lib = None
 
@@ -108,6 +108,8 @@ def load():
     L.nlse_corr_set_target_filter.argtypes = [vp, i32]
     L.nlse_corr_set_augment.argtypes = [vp, dbl, ctypes.c_uint64]
     L.nlse_mass_noalloc.argtypes = [i32, ctypes.POINTER(i64), dbl, i32, vp, vp, vp]
+    L.nlse_corr_tensor.argtypes = [vp, i32, i32, vp, i64]
+    L.nlse_corr_stage.argtypes = [vp, i32, i32]
     for f in EXPORTS:
         if f not in ("nlse_destroy", "nlse_last_error", "nlse_batch_destroy", "nlse_corr_destroy"):
             getattr(L, f).restype = ctypes.c_int
@@ -461,6 +463,23 @@ class Corrector:
 
     def apply(self, solver):
         _check(load().nlse_corr_apply(self._h, solver._h))
+
+    # ---- validation access to the training passes (nlse_corr_tensor / nlse_corr_stage)
+    TENSORS = {"X0": 0, "A1": 1, "A2": 2, "Z1": 3, "Z2": 4, "Y": 5, "dY": 6, "dZ2": 7, "dZ1": 8, "grads": 9}
+    STAGES = {"fwd1": 1, "fwd2": 2, "fwd3": 3, "wgrad3": 4, "bwd3": 5, "wgrad2": 6, "bwd2": 7, "wgrad1": 8}
+
+    def put_tensor(self, name, arr):
+        """Copy a host array (uint16 bf16 patterns or float32, layout of nlse.h) into a tensor."""
+        a = np.ascontiguousarray(arr)
+        _check(load().nlse_corr_tensor(self._h, self.TENSORS[name], 1, a.ctypes.data_as(ctypes.c_void_p), a.nbytes))
+
+    def get_tensor(self, name, shape, dtype):
+        a = np.empty(shape, dtype=dtype)
+        _check(load().nlse_corr_tensor(self._h, self.TENSORS[name], 0, a.ctypes.data_as(ctypes.c_void_p), a.nbytes))
+        return a
+
+    def stage(self, name, batch):
+        _check(load().nlse_corr_stage(self._h, self.STAGES[name], int(batch)))
 
 
 def inject(src, src_n, dst, factor, stream="current"):

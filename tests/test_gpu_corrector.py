@@ -146,3 +146,160 @@ def test_learned_gain_held_out(gpu):
     e_plain, e_learned = K.rel(plain, R), K.rel(learned, R)
     say(f"[result] E_plain(513^2) {e_plain:.3e}, E_learned {e_learned:.3e}, gain {e_plain / e_learned:.2f}")
     assert e_learned < 0.8 * e_plain
+
+
+# ----------------------------------------------------------------------------------------
+# Layer-by-layer parity.  Each GPU stage runs on seeded host tensors (nlse_corr_tensor /
+# nlse_corr_stage) and is compared with oracle/conv.py on the same tensors.  FP32 sums of
+# K products (the MFMA accumulation, and the weight gradients' fixed-order reduction) are
+# within gamma_K * sum|terms| of the exact FP64 value, gamma_K = K u / (1 - K u), u = 2^-24
+# (the standard bound for any summation order); a bf16 output is within half a bf16 unit
+# (2^-8 relative) of the exact value, widened by the error of the FP32 quantity it rounds
+# and 16 u for the hardware exponential and reciprocal in silu.
+
+U32 = 2.0 ** -24
+
+
+def gamma(k):
+    return k * U32 / (1.0 - k * U32)
+
+
+def to_bits(x):
+    """float64 values -> raw bf16 patterns (round to nearest even, as conv.bf16)."""
+    f = conv.bf16(x).astype(np.float32)
+    return (f.view(np.uint32) >> 16).astype(np.uint16)
+
+
+def from_bits(u):
+    return (np.asarray(u, dtype=np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def rand_bf16(rng, shape, scale=1.0):
+    return to_bits(rng.standard_normal(shape) * scale)
+
+
+def check_fp32_sum(got, exact, abs_terms, k, what):
+    err = np.abs(got.astype(np.float64) - exact)
+    bound = gamma(k) * abs_terms + U32 * np.abs(exact)
+    worst = float(np.max(err / np.maximum(bound, 1e-300)))
+    scale = float(np.max(np.abs(exact)))
+    say(f"[result] {what}: max |err| {err.max():.3e} (max |value| {scale:.3e}), worst err/bound {worst:.3f}")
+    assert np.all(err <= bound), what
+
+
+def check_bf16(got_bits, exact, slack, what):
+    got = from_bits(got_bits)
+    err = np.abs(got - exact)
+    bound = 2.0 ** -8 * (np.abs(exact) + slack) + slack
+    worst = float(np.max(err / np.maximum(bound, 1e-300)))
+    say(f"[result] {what}: max |err| {err.max():.3e}, worst err/bound {worst:.3f}")
+    assert np.all(err <= bound), what
+
+
+B_L, H_L, W_L = 2, 21, 45   # ragged: W is not a multiple of the 32-pixel wave tile
+
+
+def layer_setup(gpu, seed):
+    p = nontrivial_params(seed)
+    m = gpu.Corrector(H_L, W_L, max_batch=B_L)
+    m.set_params(flat(p), 1.0)
+    return m, p
+
+
+@pytest.mark.parametrize("layer", [1, 2, 3])
+def test_layer_forward_fp32_accumulators(gpu, layer):
+    """Z1 / Z2 / Y from seeded bf16 inputs: FP32 MFMA sums within gamma_K sum|terms| of the FP64
+    convolution; A1 / A2 within half a bf16 unit of bf16(silu(Z))."""
+    rng = np.random.default_rng(100 + layer)
+    m, p = layer_setup(gpu, 40 + layer)
+    cin = 8 if layer == 1 else 32
+    x = rand_bf16(rng, (B_L, H_L, W_L, cin))
+    if layer == 1:
+        x[..., 6:] = 0   # the two unused feature channels
+    m.put_tensor({1: "X0", 2: "A1", 3: "A2"}[layer], x)
+    m.stage(f"fwd{layer}", B_L)
+    W = conv.bf16(p[f"W{layer}"])
+    b = p[f"b{layer}"]
+    cout = W.shape[0]
+    xf = from_bits(x)
+    k = 9 * cin + 1
+    if layer < 3:
+        Z = m.get_tensor(f"Z{layer}", (B_L, H_L, W_L, cout), np.float32)
+        A = m.get_tensor(f"A{layer}", (B_L, H_L, W_L, cout), np.uint16)
+    else:
+        Z = m.get_tensor("Y", (B_L, H_L, W_L, cout), np.float32)
+    for i in range(B_L):
+        ex = conv.conv3x3(xf[i], W, b)
+        terms = conv.conv3x3(np.abs(xf[i]), np.abs(W), np.abs(b))
+        check_fp32_sum(Z[i], ex, terms, k, f"layer {layer} FP32 sums, sample {i}")
+        if layer < 3:
+            zerr = gamma(k) * terms + U32 * np.abs(ex)
+            # silu' is bounded by 1.1: the FP32 error of Z moves silu by at most 1.1 zerr
+            check_bf16(A[i], conv.silu(ex), 1.1 * zerr + 16 * U32 * np.abs(conv.silu(ex)),
+                       f"layer {layer} bf16 activations, sample {i}")
+
+
+@pytest.mark.parametrize("layer", [3, 2, 1])
+def test_layer_weight_gradients(gpu, layer):
+    """dW, db of each layer from seeded bf16 inputs and output gradients: the FP32 reduction
+    over the batch's pixels within gamma_K sum|terms| of the FP64 sums."""
+    rng = np.random.default_rng(200 + layer)
+    m, p = layer_setup(gpu, 50 + layer)
+    cin = 8 if layer == 1 else 32
+    x = rand_bf16(rng, (B_L, H_L, W_L, cin))
+    if layer == 1:
+        x[..., 6:] = 0
+    if layer == 3:
+        g = np.zeros((B_L, H_L, W_L, 8), np.uint16)
+        g[..., :2] = rand_bf16(rng, (B_L, H_L, W_L, 2), 1e-2)
+        cout = 2
+    else:
+        g = rand_bf16(rng, (B_L, H_L, W_L, 32), 1e-2)
+        cout = 32
+    m.put_tensor({1: "X0", 2: "A1", 3: "A2"}[layer], x)
+    m.put_tensor({1: "dZ1", 2: "dZ2", 3: "dY"}[layer], g)
+    m.put_tensor("grads", np.zeros(m.nparam, np.float32))
+    m.stage(f"wgrad{layer}", B_L)
+    gr = m.get_tensor("grads", (m.nparam,), np.float32).astype(np.float64)
+    xf, gf = from_bits(x), from_bits(g)[..., :cout]
+    ex_w = sum(conv.weight_grad(xf[i], gf[i]) for i in range(B_L))
+    ab_w = sum(conv.weight_grad(np.abs(xf[i]), np.abs(gf[i])) for i in range(B_L))
+    ex_b = gf.sum(axis=(0, 1, 2))
+    ab_b = np.abs(gf).sum(axis=(0, 1, 2))
+    offs = {"W1": (0, 2304), "b1": (2304, 2336), "W2": (2336, 11552), "b2": (11552, 11584),
+            "W3": (11584, 12160), "b3": (12160, 12162)}
+    k = B_L * H_L * W_L
+    a, e = offs[f"W{layer}"]
+    check_fp32_sum(gr[a:e], ex_w.ravel(), ab_w.ravel(), k, f"dW{layer}")
+    a, e = offs[f"b{layer}"]
+    check_fp32_sum(gr[a:e], ex_b, ab_b, k, f"db{layer}")
+
+
+@pytest.mark.parametrize("layer", [3, 2])
+def test_layer_input_gradients(gpu, layer):
+    """dZ2 = bf16(conv^T(dY, W3) silu'(Z2)) and dZ1 = bf16(conv^T(dZ2, W2) silu'(Z1)) from seeded
+    inputs: within half a bf16 unit of the exact value, widened by the FP32 sum's bound."""
+    rng = np.random.default_rng(300 + layer)
+    m, p = layer_setup(gpu, 60 + layer)
+    if layer == 3:
+        g = np.zeros((B_L, H_L, W_L, 8), np.uint16)
+        g[..., :2] = rand_bf16(rng, (B_L, H_L, W_L, 2), 1e-2)
+        gf = from_bits(g)[..., :2]
+        k = 9 * 8
+    else:
+        g = rand_bf16(rng, (B_L, H_L, W_L, 32), 1e-2)
+        gf = from_bits(g)
+        k = 9 * 32
+    z = (rng.standard_normal((B_L, H_L, W_L, 32)) * 2.0).astype(np.float32)
+    m.put_tensor({3: "dY", 2: "dZ2"}[layer], g)
+    m.put_tensor({3: "Z2", 2: "Z1"}[layer], z)
+    m.stage(f"bwd{layer}", B_L)
+    out = m.get_tensor({3: "dZ2", 2: "dZ1"}[layer], (B_L, H_L, W_L, 32), np.uint16)
+    W = conv.bf16(p[f"W{layer}"])
+    for i in range(B_L):
+        s = conv.conv3x3_transpose(gf[i], W)
+        s_abs = conv.conv3x3_transpose(np.abs(gf[i]), np.abs(W))
+        d = conv.dsilu(z[i].astype(np.float64))
+        ex = s * d
+        slack = (gamma(k) * s_abs + U32 * np.abs(s)) * np.abs(d) + 16 * U32 * np.abs(ex)
+        check_bf16(out[i], ex, slack, f"input gradient of layer {layer}, sample {i}")

@@ -204,3 +204,71 @@ def test_msd_with_potential(gpu, orc, dim, prec):
     out = sol.get_field()
     sol.close()
     assert rel(out, P.rk4(psi, nst, dt)) <= TOL[prec]
+
+
+def _case(dim):
+    if dim == 1:
+        n, psi = I.dark_plane(1, 0.125, lo=-8.0, hi=8.0, x0=-7.0)
+        rng = np.random.default_rng(3)
+        psi = psi + 1e-2 * (rng.standard_normal(psi.shape) + 1j * rng.standard_normal(psi.shape))
+        return n[0], 0.125, psi
+    g, psi = vortex_case(90) if dim == 2 else ring_case(30)
+    return g.n, g.h, psi
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_msd_tiny_field(gpu, orc, dim, prec):
+    """The whole field scaled by 1e-20 with s = 0 (linear, so the solution scales exactly).
+    |Psi_{b-1}|^2 ~ 1e-40 is subnormal in FP32: the ratios Re(D_{b-1}/Psi_{b-1}) and
+    Im(F_{b-1}/Psi_{b-1}) of Eqs. msdbc_lap / msdbc_ut must still come out right (the kernels
+    scale numerator and denominator by a power of two before dividing)."""
+    n, h, psi = _case(dim)
+    psi = 1e-20 * psi
+    P = orc.Problem(dim, n, h, 0.5, 0.0, bc="msd")
+    dt = 0.5 * P.max_dt(psi)
+    nst = 20 if dim < 3 else 6
+    say(f"[case] msd {dim}d tiny field (|Psi| ~ 1e-20), s = 0, {prec}, {nst} steps")
+    sol = gpu.Solver(dim, n, h, 0.5, 0.0, None, "msd", prec)
+    sol.set_field(psi.astype(sol.dtype))
+    sol.step(nst, dt)
+    out = sol.get_field()
+    sol.close()
+    ref = P.rk4(psi, nst, dt)
+    e = rel(out, ref)
+    say(f"[result] msd {dim}d tiny field {prec}: rel L2 {e:.3e}")
+    assert np.isfinite(out).all()
+    assert e <= TOL[prec]
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_msd_zero_b_minus_1(gpu, orc, dim, prec):
+    """Psi_{b-1} = 0 at some boundary neighbours (reading: the ratio term of Eq. msdbc_lap and the
+    phase rate of Eq. msdbc_ut are dropped there): GPU against the oracle."""
+    n, h, psi = _case(dim)
+    psi = psi.copy()
+    if dim == 1:
+        psi[1] = 0.0
+        psi[-2] = 0.0
+    elif dim == 2:
+        psi[10:30, 1] = 0.0          # the x = 0 face's inner neighbours
+        psi[-2, 40:60] = 0.0         # the y = ny face's
+        psi[1, 1] = 0.0              # the corner's diagonal neighbour
+    else:
+        psi[5:12, 5:12, 1] = 0.0
+        psi[1, 8:20, 8:20] = 0.0
+    P = orc.Problem(dim, n, h, 0.5, -1.0, bc="msd")
+    dt = 0.5 * P.max_dt(psi)
+    nst = 12 if dim < 3 else 4
+    say(f"[case] msd {dim}d with Psi_(b-1) = 0 on part of the boundary, {prec}, {nst} steps")
+    sol = gpu.Solver(dim, n, h, 0.5, -1.0, None, "msd", prec)
+    sol.set_field(psi.astype(sol.dtype))
+    sol.step(nst, dt)
+    out = sol.get_field()
+    sol.close()
+    ref = P.rk4(psi, nst, dt)
+    e = rel(out, ref)
+    say(f"[result] msd {dim}d zero b-1 {prec}: rel L2 {e:.3e}")
+    assert np.isfinite(out).all()
+    assert e <= TOL[prec]
