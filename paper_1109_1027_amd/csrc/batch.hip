@@ -64,9 +64,7 @@ __global__ __launch_bounds__(64 * NW) void batch2d_kernel(const BatchItem *items
 {
     extern __shared__ unsigned char smem[];
     __shared__ int s_item;
-    constexpr int FR = wave2d::face_rows<Q>();
-    auto *sdx = reinterpret_cast<C<R>(*)[2][FR]>(smem);                  // [NW][2][FR]
-    auto *sdy = reinterpret_cast<C<R>(*)[2][64]>(smem + sizeof(C<R>) * NW * 2 * FR);
+    auto *stg = reinterpret_cast<wave2d::Staging<R, Q> *>(smem);   // [NW], one per wave
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (;;) {
         __syncthreads();
@@ -95,7 +93,7 @@ __global__ __launch_bounds__(64 * NW) void batch2d_kernel(const BatchItem *items
             a.psi_in = cur;
             a.psi_out = nxt;
             for (int task = wv; task < tasks; task += NW)
-                wave2d::step2d_wave<R, M, Q>(a, task % strips, task / strips, threadIdx.x & 63, sdx[wv], sdy[wv]);
+                wave2d::step2d_wave<R, M, Q>(a, task % strips, task / strips, threadIdx.x & 63, stg[wv]);
             __syncthreads();   // Psi^{n+1} complete before any task reads it
             void *t = cur;
             cur = nxt;
@@ -172,7 +170,7 @@ static hipError_t launch_batch_q(const BatchLaunch &L, hipStream_t st)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (L.n2d > 0) {
-        const size_t lds = sizeof(C<R>) * NW * 2 * (wave2d::face_rows<Q>() + 64);
+        const size_t lds = sizeof(wave2d::Staging<R, Q>) * NW;
         hipLaunchKernelGGL((batch2d_kernel<R, M, Q, NW>), dim3(L.grid2d), dim3(64 * NW), lds, st, L.items, L.order,
                            L.n2d, L.queue, L.nsteps);
         e = hipGetLastError();

@@ -113,6 +113,11 @@ struct Field {
     {
         return d2<R>(psi(step(q, a, -1)), psi(q), psi(step(q, a, 1)), ih2);
     }
+    // h^2 delta_a^2 Psi at q, unscaled (as the interior kernels form it)
+    __device__ __forceinline__ C<R> d2u_a(const Node &q, int a) const
+    {
+        return d2u<R>(psi(step(q, a, -1)), psi(q), psi(step(q, a, 1)));
+    }
 };
 
 // The face value D^a_b at the face node b (normal to a, on no other face): the MSD step-1
@@ -174,28 +179,31 @@ struct KnownFace {
 };
 
 // F at the interior node q, per-axis 2SHOC (Eqs. 2d2shocMs1-2, 3d2shocMs1-2) with the face
-// values where q's neighbour along an axis is a boundary node.
+// values where q's neighbour along an axis is a boundary node.  Formed exactly as the interior
+// stage kernels form it (unscaled second differences, face values times h^2, a and 1/h^2 folded
+// into the step-2 coefficients), so F_{b-1} of the boundary rule is bitwise the interior
+// kernels' F at b-1.
 template <typename IN, typename R, int DIM, typename Faces>
 __device__ C<R> interior_F(const Field<IN, R> &f, const Faces &face_value, const Coeffs &cf, const Node &q)
 {
-    const R ih2 = (R)cf.ih2, c76 = (R)cf.c76, c112 = (R)cf.c112;
+    const Step2Coef<R> lc = step2_coef<R>(cf.a, cf.c76, cf.c112, cf.ih2);
     C<R> dc[3], dl[3], dr[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         dc[a] = dl[a] = dr[a] = czero<R>();
         if (a >= DIM) continue;
-        dc[a] = f.d2a(q, a, ih2);
+        dc[a] = f.d2u_a(q, a);
         const Node lo = step(q, a, -1), hi = step(q, a, 1);
-        dl[a] = lo.at(a) == 0 ? face_value(a, lo) : f.d2a(lo, a, ih2);
-        dr[a] = hi.at(a) == ext(f.L, a) ? face_value(a, hi) : f.d2a(hi, a, ih2);
+        dl[a] = lo.at(a) == 0 ? unscaled<R>(face_value(a, lo), lc.h2) : f.d2u_a(lo, a);
+        dr[a] = hi.at(a) == ext(f.L, a) ? unscaled<R>(face_value(a, hi), lc.h2) : f.d2u_a(hi, a);
     }
-    C<R> lap;
+    C<R> alap;
     if constexpr (DIM == 2) {
-        lap = lap2<R>(dc[0], dc[1], dl[0], dr[0], dl[1], dr[1], c76, c112);
+        alap = lap2a<R>(dc[0], dc[1], dl[0], dr[0], dl[1], dr[1], lc.A76, lc.A112);
     } else {
-        lap = lap3<R>(dc[0], dc[1], dc[2], dl[0], dr[0], dl[1], dr[1], dl[2], dr[2], c76, c112);
+        alap = lap3<R>(dc[0], dc[1], dc[2], dl[0], dr[0], dl[1], dr[1], dl[2], dr[2], lc.A76, lc.A112);
     }
-    return rhs<R>(lap, f.psi(q), f.pot(q), (R)cf.a, (R)cf.s);
+    return rhs_a<R>(alap, f.psi(q), f.pot(q), (R)cf.s);
 }
 
 // Im(F_q / Psi_q), 0 when Psi_q = 0.

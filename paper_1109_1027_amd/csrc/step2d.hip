@@ -36,15 +36,12 @@ constexpr int NW = 4;      // waves per block (independent)
 template <typename R, typename M, int Q, int PD, int ST>
 __global__ __launch_bounds__(256) void step2d_kernel(Step2DArgs A, int strips, int waves)
 {
-    constexpr int FR = wave2d::face_rows<Q>();
-    // Wave-private staging of the boundary-face values (written and read by the
-    // same wave only, so no barrier is needed).
-    __shared__ C<R> sdx[NW][2][FR];
-    __shared__ C<R> sdy[NW][2][64];
+    // Wave-private staging (written and read by the same wave only, so no barrier is needed).
+    __shared__ wave2d::Staging<R, Q> stg[NW];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int w = (int)xcd_remap(blockIdx.x, gridDim.x) * NW + wv;
     if (w >= waves) return;                 // whole waves only; the kernel has no barriers
-    wave2d::step2d_wave<R, M, Q, PD, ST>(A, w % strips, w / strips, threadIdx.x & 63, sdx[wv], sdy[wv]);
+    wave2d::step2d_wave<R, M, Q, PD, ST>(A, w % strips, w / strips, threadIdx.x & 63, stg[wv]);
 }
 
 template <typename R, typename M, int ST, int Q, int PD = 1>

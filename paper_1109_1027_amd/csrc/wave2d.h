@@ -23,20 +23,44 @@ template <int Q> constexpr int face_rows() { return 9 * Q + HALO; }      // rows
 __host__ __device__ inline int strips(int64_t nx) { return (int)((nx - 1 + SW - 1) / SW); }
 template <int Q> __host__ __device__ inline int segments(int64_t ny) { return (int)((ny - 1 + seg_rows<Q>() - 1) / seg_rows<Q>()); }
 
-// sdx: [2][face_rows<Q>()] (D^x on the faces x = 0 and x = nx for the task's
-// rows), sdy: [2][64] (D^y on the faces y = 0 and y = ny for its columns);
-// wave-private LDS, rewritten by every call.  strip < strips(nx) and
-// seg < segments<Q>(ny), wave-uniform; the field has < 2^31 elements.
+constexpr int RP = 2;               // zero entries on each side of a ring row
+constexpr int RS = 64 + 2 * RP;     // ring row stride
+
+// A wave's private LDS, rewritten by every call.
+//   sdx: D^x on the faces x = 0 and x = nx for the task's rows,
+//   sdy: D^y on the faces y = 0 and y = ny for its columns,
+//   ring: the last three input rows of each stage, lane l at entry l + RP; the entries
+//         beyond the wave read zero, as the lanes shifted in by a DPP wave shift do.
+template <typename R, int Q>
+struct Staging {
+    C<R> sdx[2][face_rows<Q>()];
+    C<R> sdy[2][64];
+    C<R> ring[4][3][RS];
+};
+
+// Orders the wave's LDS accesses on either side for the compiler.  Lanes exchange values
+// through the staging (a lane reads what its neighbours wrote), which the per-thread view of
+// the program does not see as a dependence; the LDS executes one wave's accesses in issue
+// order, so keeping the issue order is all the exchange needs.
+__device__ __forceinline__ void lds_order()
+{
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// strip < strips(nx) and seg < segments<Q>(ny), wave-uniform; the field has < 2^31 elements.
 // ST selects the Laplacian as in the stage kernels: 0 the per-axis 2SHOC form, 1 the
 // non-compact five-point stencil (ghosts 2 Psi_b - Psi_{b-+1} + h^2 D^a_b beyond a face), 2 the
 // second-order CD.
 template <typename R, typename M, int Q, int PD = 1, int ST = 0>
-__device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int seg, int lane,
-                                            C<R> (*sdx)[face_rows<Q>()], C<R> (*sdy)[64])
+__device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int seg, int lane, Staging<R, Q> &S)
 {
+    auto &sdx = S.sdx;
+    auto &sdy = S.sdy;
+    auto &ring = S.ring;
     constexpr int SEG = seg_rows<Q>();
     constexpr int FR = face_rows<Q>();
-    __builtin_amdgcn_wave_barrier();        // earlier reads of the staging come first
+    lds_order();        // earlier reads of the staging come first
     const int nx = (int)A.L.nx, ny = (int)A.L.ny, px = (int)A.L.px, ox = (int)A.L.ox;
     const int xs = 1 + SW * strip - HALO;   // column of lane 0
     const int x = xs + lane;
@@ -45,7 +69,11 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
     const bool xface = x == 0 || x == nx;
     const bool wlane = xint && lane >= HALO && lane < HALO + SW;
     const bool has_face = xs <= 0 || xs + 63 >= nx;   // wave-uniform
-    const int y0 = 1 + SEG * seg, y1 = min(y0 + SEG, ny);
+    // The task stores rows ys .. y1-1.  Its window of rows starts at y0 = ys, except in the last
+    // segment, whose window ends at the face (y0 = ny - SEG, overlapping the segment before it):
+    // then the face rows meet the pipeline only in the last group.
+    const int ys = 1 + SEG * seg, y1 = min(ys + SEG, ny);
+    const int y0 = seg == segments<Q>(ny) - 1 ? max(1, ny - SEG) : ys;
     const int jb = y0 - HALO;               // row of Psi^n that enters at t = 0
 
     const R s = (R)A.c.s;
@@ -75,7 +103,14 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
             sdx[1][i] = ok ? unscaled<R>(DBx[ny + 1 + r], lc.h2) : czero<R>();
         }
     }
-    __builtin_amdgcn_wave_barrier();
+    if (lane < 2 * RP) {
+        const int e = lane < RP ? lane : RS - 2 * RP + lane;
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) ring[st][q][e] = czero<R>();
+    }
+    lds_order();
 
     C<R> U[4][3], D[4][3], Kq[9];
     C<R> Uq[4][5];   // non-compact stencil: each stage's input rows m-4 .. m (a shift queue)
@@ -113,14 +148,21 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
 #pragma unroll
     for (int d = 0; d < PD; ++d) load_row(jb + d, pf[d], vf[d]);
 
-    // One group of nine rows.  WARM: the group may hold rows t < 16, where a stage's output is
-    // skipped while its inputs are still filling the pipeline (t < 4 (st + 1)); the first two
-    // groups run with that test, the rest without it.
-    auto group = [&](const int g, auto warm) {
+    // One group of nine rows.  A PLAIN group needs none of the tests of the general one: it holds
+    // no row t < 16 (where a stage's output is skipped while its inputs are still filling the
+    // pipeline, t < 4 (st + 1)), no stage meets a face row (m - 1 = 0 or ny), every output row
+    // r lies in 1 .. ny-1 and below y1, and the face columns take their values by a select.
+    // That holds for g >= 2 when the newest row of stage 1 stays below the face,
+    // jb + 9 g + 8 <= ny.
+    auto group = [&](const int g, auto plain_t) {
+        constexpr bool plain = decltype(plain_t)::value;
 #pragma unroll
         for (int p = 0; p < 9; ++p) {
             const int t = 9 * g + p;
             const int j = jb + t;
+            // Ring rows read in this row were written two rows ago; within the row, reads and
+            // writes use different ring slots.
+            lds_order();
             P[p] = pf[0];
             Vq[p] = vf[0];
 #pragma unroll
@@ -142,8 +184,23 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                 }
             }
             C<R> in = cvt<R, M>(P[p]);
+            // x neighbours of the row each stage differentiates (row m-2, written two rows
+            // ago): read one stage ahead, before this row's ring writes
+            auto read_nb = [&](int st, C<R>(&nb)[4]) {
+                const C<R> *row = ring[st][q1] + RP + lane;
+                nb[1] = row[-1];
+                nb[2] = row[1];
+                if constexpr (ST == 1) {
+                    nb[0] = row[-2];
+                    nb[3] = row[2];
+                }
+            };
+            C<R> nb[4] = {}, nbn[4] = {};
+            read_nb(0, nb);
+            ring[0][q0][RP + lane] = in;
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
+                if (st < 3) read_nb(st + 1, nbn);
                 const int m = j - 2 * st;   // newest input row of this stage
                 if constexpr (ST == 1) {
 #pragma unroll
@@ -152,59 +209,76 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                 } else {
                     U[st][q0] = in;
                     C<R> dy = d2u<R>(U[st][q1], U[st][q2], U[st][q0]);   // h^2 D^y at row m-1
-                    if (m - 1 == 0) dy = sdy[0][lane];
-                    if (m - 1 == ny) dy = sdy[1][lane];
+                    if (!plain) {
+                        if (m - 1 == 0) dy = sdy[0][lane];
+                        if (m - 1 == ny) dy = sdy[1][lane];
+                    }
                     D[st][q0] = dy;
                 }
                 C<R> outv = czero<R>();
-                if (!decltype(warm)::value || t >= 4 * (st + 1)) {    // earlier output rows feed nothing
+                if (plain || t >= 4 * (st + 1)) {    // earlier output rows feed nothing
                     const int r = m - 2;    // output row
                     const int kr = (p + 18 - 2 * (st + 1)) % 9;
                     const C<R> u = ST == 1 ? Uq[st][2] : U[st][q1];
                     C<R> F;
                     if constexpr (ST == 0) {
-                        C<R> dx = d2u<R>(clane_prev<R>(u), u, clane_next<R>(u));
-                        if (has_face && xface) dx = fv[st];   // fv[st] is row r of the face
+                        C<R> dx = d2u<R>(nb[1], u, nb[2]);
+                        if (plain) {
+                            if (xface) dx = fv[st];   // fv[st] is row r of the face (set where xface)
+                        } else if (has_face) {        // wave-uniform: only the edge strips select
+                            if (xface) dx = fv[st];
+                            asm volatile("" : "+v"(dx.x), "+v"(dx.y));   // keeps the branch
+                        }
                         const C<R> alap = lap2a<R>(dx, D[st][q2], clane_prev<R>(dx), clane_next<R>(dx), D[st][q1],
                                                    D[st][q0], lc.A76, lc.A112);
                         F = rhs_a<R>(alap, u, Vq[kr], s);
                     } else if constexpr (ST == 2) {   // a/h^2 (D^x + D^y) from the unscaled differences
-                        const C<R> dx = d2u<R>(clane_prev<R>(u), u, clane_next<R>(u));
+                        const C<R> dx = d2u<R>(nb[1], u, nb[2]);
                         F = rhs_a<R>(cscale<R>(aih2, cadd<R>(dx, D[st][q2])), u, Vq[kr], s);
                     } else {   // five-point differences along x (lanes) and y (the row queue)
-                        const C<R> xm1 = clane_prev<R>(u), xp1 = clane_next<R>(u);
-                        C<R> xm2 = clane_prev<R>(xm1), xp2 = clane_next<R>(xp1);
+                        const C<R> xm1 = nb[1], xp1 = nb[2];
+                        C<R> xm2 = nb[0], xp2 = nb[3];
                         if (has_face) {   // fv[st]: the face value of row r next to lane x = 1 / nx - 1
                             if (x == 1) xm2 = ghost<R>(xm1, u, fv[st]);
                             if (x == nx - 1) xp2 = ghost<R>(xp1, u, fv[st]);
                         }
                         C<R> ym2 = Uq[st][0], yp2 = Uq[st][4];
-                        if (r == 1) ym2 = ghost<R>(Uq[st][1], u, sdy[0][lane]);
-                        if (r == ny - 1) yp2 = ghost<R>(Uq[st][3], u, sdy[1][lane]);
+                        if (!plain) {
+                            if (r == 1) ym2 = ghost<R>(Uq[st][1], u, sdy[0][lane]);
+                            if (r == ny - 1) yp2 = ghost<R>(Uq[st][3], u, sdy[1][lane]);
+                        }
                         const C<R> lap = cadd<R>(d4nc<R>(xm2, xm1, u, xp1, xp2, i12h2),
                                                  d4nc<R>(ym2, Uq[st][1], u, Uq[st][3], yp2, i12h2));
                         F = rhs<R>(lap, u, Vq[kr], aR, s);
                     }
-                    const R rowf = (r >= 1 && r < ny) ? R(1) : R(0);   // wave-uniform
+                    const R rowf = (plain || (r >= 1 && r < ny)) ? R(1) : R(0);   // wave-uniform
                     if (st == 0) {
                         Kq[kr] = F;
-                        outv = cvt<R, M>(axpy_m<R, M>(P[kr], ckl[0] * rowf, F));
+                        outv = cvt<R, M>(axpy_m<R, M>(P[kr], plain ? ckl[0] : ckl[0] * rowf, F));
                     } else if (st < 3) {
                         Kq[kr] = kacc<R>(Kq[kr], F);
-                        outv = cvt<R, M>(axpy_m<R, M>(P[kr], ckl[st] * rowf, F));
-                    } else if (wlane && r >= y0 && r < y1) {
+                        outv = cvt<R, M>(axpy_m<R, M>(P[kr], plain ? ckl[st] : ckl[st] * rowf, F));
+                    } else if (wlane && r >= ys && (plain || r < y1)) {
                         pout[r * px + x + ox] = axpy_m<R, M>(P[kr], ck[3], cadd<R>(Kq[kr], F));
                     }
                 }
                 in = outv;
+                if (st < 3) {
+                    ring[st + 1][q0][RP + lane] = in;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) nb[i] = nbn[i];
+                }
             }
         }
     };
     static_assert(Q >= 2, "the first two groups are the warm-up");
+    const int gp = min(Q, max(2, (ny - jb - 8) / 9 + 1));   // groups 2 .. gp-1 are plain
 #pragma unroll 1
-    for (int g = 0; g < 2; ++g) group(g, std::true_type{});
+    for (int g = 0; g < 2; ++g) group(g, std::false_type{});
 #pragma unroll 1
-    for (int g = 2; g < Q; ++g) group(g, std::false_type{});
+    for (int g = 2; g < gp; ++g) group(g, std::true_type{});
+#pragma unroll 1
+    for (int g = gp; g < Q; ++g) group(g, std::false_type{});
 }
 
 }  // namespace wave2d
