@@ -147,16 +147,20 @@ const char *nlse_last_error(void);
 
 /* Number of kernel launches one RK4 step enqueues for this context with its current
  * variant: 4 for the 2D/3D stage kernels (8 under MSD: a boundary launch, face values
- * and boundary nodes, before each stage), 1 for the 2D whole-step kernels and 2 for the
- * 3D two-stage kernels (Dirichlet only); 1D contexts advance all steps in one launch and
- * report 0.  For throughput accounting. */
+ * and boundary nodes, before each stage), 1 for the 2D whole-step kernels (Dirichlet and
+ * MSD) and 2 for the 3D two-stage kernels (Dirichlet only); 1D contexts advance all steps in
+ * one launch and report 0.  For throughput accounting. */
 int nlse_launches_per_step(const nlse_ctx *c);
 
 /* Kernel variants.  2D: 0-2 are the stage kernels (one launch per RK4 stage, tiles of
  * 64 columns x 8, 4 or 16 rows per wave); 3-9 the whole-step kernels (one launch per RK4
  * step, Sec. 3.1 with all four stages fused; a wave walks a 64-column strip down a segment
  * of 29, 20, 38, 56, 11, 47 or 29 rows, the last with two rows of Psi^n in flight instead
- * of one; offered under Dirichlet when the padded field has fewer than 2^31 elements).
+ * of one; offered when the padded field has fewer than 2^31 elements).  Under MSD (2D, at
+ * least 2 intervals per axis) the whole-step kernels form the face values and the boundary
+ * nodes of Eqs. msdbc_lap and msdbc_ut themselves, and the strips that hold a face column
+ * take segments of about half as many rows; their results equal the MSD stage kernels' to the
+ * last place except for rare one-unit differences of it that start on the face y = 0. */
  * 3D: 0-3 stage kernels with 64 x 4 or 64 x 8 column tiles marching 16, 32 or 64 planes;
  * 4-6 (Dirichlet, fields below 2^31 elements) two launches per step, each fusing two stages
  * (1+2, 3+4) on 64 x 16 or 64 x 8 column tiles marching 32 or 64 planes.

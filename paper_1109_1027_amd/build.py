@@ -25,9 +25,15 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
+# Per-file flags.  The 2D whole-step kernels unroll their nine-row loop completely (every register
+# ring index a constant); the MSD instances' loop body exceeds LLVM's default size limit for a
+# requested full unroll, and a rolled loop would put the rings in scratch memory.
+EXTRA = {"step2d.hip": ["-mllvm", "-pragma-unroll-threshold=40000"]}
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")

@@ -88,6 +88,7 @@ __global__ __launch_bounds__(64 * NW) void batch2d_kernel(const BatchItem *items
         a.ck[3] = dt / 6.0;
         a.variant = 0;
         a.stencil = 0;
+        a.msd = 0;
         void *cur = I.psi, *nxt = I.psi2;
         for (int64_t step = 0; step < nsteps; ++step) {
             a.psi_in = cur;

@@ -49,6 +49,7 @@ struct Step2DArgs {
     double ck[4];        // k/2, k/2, k, k/6
     int variant;
     int stencil;         // 0 2SHOC, 1 non-compact fourth order, 2 second-order CD
+    int msd;             // 1: MSD boundary (2SHOC only; boundary nodes of psi_out written too, DB unused)
 };
 hipError_t launch_step2d(Prec prec, const Step2DArgs &a, hipStream_t st);
 int step2d_variants();

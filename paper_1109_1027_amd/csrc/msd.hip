@@ -126,6 +126,7 @@ struct Field {
 template <typename IN, typename R, int DIM>
 __device__ __forceinline__ C<R> face_closure(const Field<IN, R> &f, const Coeffs &cf, int a, const Node &b)
 {
+#pragma clang fp contract(off)
     const int side = b.at(a) == 0 ? 0 : 1;
     const R ih2 = (R)cf.ih2, s = (R)cf.s;
     const Node q = step(b, a, side ? -1 : 1);
@@ -301,8 +302,7 @@ __global__ __launch_bounds__(256) void msd_stage_kernel(Field<IN, R> f, StageArg
         const Node q = inner(L, b);
         const C<R> uq = f.psi(q);
         ub = f.psi(b);
-        const R w = phase_rate<R>(interior_F<IN, R, DIM>(f, faces, A.c, q), uq);
-        F = mk<R>(-w * ub.y, w * ub.x);
+        F = msd_fb<R>(phase_rate<R>(interior_F<IN, R, DIM>(f, faces, A.c, q), uq), ub);
     }
     if (face) {
         C<R> *dst = a == 0 ? DBx : a == 1 ? DBy : DBz;

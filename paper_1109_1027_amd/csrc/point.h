@@ -181,6 +181,16 @@ __device__ __forceinline__ R im_div(C<R> F, C<R> u)
     return (fy * ux - fx * uy) / (ux * ux + uy * uy);
 }
 
+// MSD time derivative on a boundary node (Sec. 3.2, Eq. msdbc_ut): i w Psi_b with
+// w = Im(F_{b-1} / Psi_{b-1}).  Contraction off, so that the products are rounded before any
+// sum they enter, whichever kernel forms them.
+template <typename R>
+__device__ __forceinline__ C<R> msd_fb(R w, C<R> ub)
+{
+#pragma clang fp contract(off)
+    return mk<R>(-w * ub.y, w * ub.x);
+}
+
 // K_tot accumulation of stages 2 and 3: K + 2F (2F is exact).
 template <typename R>
 __device__ __forceinline__ C<R> kacc(C<R> k, C<R> F)

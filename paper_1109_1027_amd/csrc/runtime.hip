@@ -119,7 +119,8 @@ static hipError_t launch_stage(nlse_ctx *c, int stage, double dt, int variant)
 // whole-step kernels (their 32-bit offsets need fields below 2^31 elements).
 static bool step2d_ok(const nlse_ctx *c)
 {
-    return c->p.ndim == 2 && c->p.bc == NLSE_BC_DIRICHLET && c->L.total < (int64_t(1) << 31);
+    const bool bc_ok = c->p.bc == NLSE_BC_DIRICHLET || (c->p.bc == NLSE_BC_MSD && c->L.nx >= 2 && c->L.ny >= 2);
+    return c->p.ndim == 2 && bc_ok && c->L.total < (int64_t(1) << 31);
 }
 
 // 3D variants: [0, stage3d_variants()) the stage kernels, the rest the two-stage pairs
@@ -182,6 +183,7 @@ static hipError_t launch_whole_step(nlse_ctx *c, double dt, int variant)
     a.ck[3] = dt / 6.0;
     a.variant = variant - stage2d_variants();
     a.stencil = c->stencil;
+    a.msd = c->p.bc == NLSE_BC_MSD;
     hipError_t e = launch_step2d(c->prec, a, c->stream);
     if (e == hipSuccess) std::swap(c->psi, c->psi2);
     return e;

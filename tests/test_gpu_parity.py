@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import nlse_inputs as I
+from parity_util import line_err, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -46,10 +47,6 @@ def run_both(gpu, orc, spec, prec, nsteps, dt=None, frac=0.5):
     return g, ref, s, P
 
 
-def rel(a, b):
-    return float(np.linalg.norm((np.asarray(a, np.complex128) - b).ravel()) / np.linalg.norm(b.ravel()))
-
-
 def with_random_boundary(spec, seed=5, amp=0.3):
     """Same problem with non-zero (random, fixed) Dirichlet boundary values."""
     rng = np.random.default_rng(seed)
@@ -67,6 +64,7 @@ def test_2d_gp_parity(gpu, orc, prec, n):
     sp = I.config_gp2d(n=n)
     g, ref, s, P = run_both(gpu, orc, sp, prec, 30)
     assert rel(g, ref) <= TOL[prec], rel(g, ref)
+    assert line_err(g, ref) <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -75,6 +73,7 @@ def test_2d_nonzero_boundary_parity(gpu, orc, prec):
     sp = with_random_boundary(I.config_gp2d(n=131))
     g, ref, s, P = run_both(gpu, orc, sp, prec, 25)
     assert rel(g, ref) <= TOL[prec]
+    assert line_err(g, ref) <= TOL[prec]
     m = sp.grid.boundary_mask()
     got = g.astype(np.complex128)[m]
     want = sp.psi0[m].astype(np.complex64 if prec == "f32" else np.complex128)
@@ -107,6 +106,7 @@ def test_2d_full_size_two_steps(gpu, orc):
     for prec in ("f64", "f32"):
         g, ref, s, P = run_both(gpu, orc, sp, prec, 2)
         assert rel(g, ref) <= TOL[prec], (prec, rel(g, ref))
+        assert line_err(g, ref) <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
@@ -152,6 +152,7 @@ def test_1d_soliton_full_run(gpu, orc, prec):
     assert nsteps == 3955
     g, ref, s, _ = run_both(gpu, orc, sp, prec, nsteps, dt)
     assert rel(g, ref) <= TOL[prec]
+    assert line_err(g, ref) <= TOL[prec]
     (x,) = sp.grid.coords()
     exact = I.bright_soliton(x, 10.0, 1.0, 1.0, 1.0, 0.5)
     err, err_ref = rel(g, exact), rel(ref, exact)
@@ -169,6 +170,7 @@ def test_1d_msd_dark_soliton(gpu, orc, prec):
     sp = I.paper_fig1(0.25)
     g, ref, s, P = run_both(gpu, orc, sp, prec, 2000, dt=0.0005)
     assert rel(g, ref) <= TOL[prec]
+    assert line_err(g, ref) <= TOL[prec]
 
 
 @pytest.mark.parametrize("n,prec", [(2, "f64"), (3, "f64"), (1023, "f64"), (5119, "f64"), (2, "f32"),
@@ -183,6 +185,7 @@ def test_1d_sizes(gpu, orc, n, prec):
     sp = I.ProblemSpec("sizes1d", g, 1.0, 1.0, 0.05 * x * x, psi, "dirichlet")
     gg, ref, s, P = run_both(gpu, orc, sp, prec, 40)
     assert rel(gg, ref) <= TOL[prec]
+    assert line_err(gg, ref) <= TOL[prec]
 
 
 # ------------------------------------------------------------------- 3D --
@@ -192,18 +195,21 @@ def test_3d_gp_parity(gpu, orc, prec):
     sp = I.config_gp3d(n=70)
     g, ref, s, P = run_both(gpu, orc, sp, prec, 8)
     assert rel(g, ref) <= TOL[prec], rel(g, ref)
+    assert line_err(g, ref) <= TOL[prec]
 
 
 def test_3d_nonzero_boundary_parity(gpu, orc):
     sp = with_random_boundary(I.config_gp3d(n=37))
     g, ref, s, P = run_both(gpu, orc, sp, "f64", 6)
     assert rel(g, ref) <= 1e-12
+    assert line_err(g, ref) <= 1e-12
 
 
 def test_3d_small(gpu, orc):
     sp = I.config_gp3d(n=4)
     g, ref, s, P = run_both(gpu, orc, sp, "f64", 3)
     assert rel(g, ref) <= 1e-12
+    assert line_err(g, ref) <= 1e-12
 
 
 # ---------------------------------------------------------- diagnostics --
@@ -439,6 +445,7 @@ def test_1d_variants_bitwise_identical(gpu, orc, prec, n, bc):
     P = orc.Problem.from_spec(sp)
     ref = P.rk4(sp.psi0, 25, 0.5 * P.max_dt(sp.psi0))
     assert rel(outs[0], ref) <= TOL[prec]
+    assert line_err(outs[0], ref) <= TOL[prec]
 
 
 def test_1d_autotune_keeps_state(gpu):

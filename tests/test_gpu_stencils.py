@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import nlse_inputs as I
+from parity_util import line_err, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -30,10 +31,6 @@ def gpu():
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def rel(a, b):
-    return float(np.linalg.norm((np.asarray(a, np.complex128) - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
 def with_random_boundary(spec, seed=5, amp=0.3):
@@ -63,9 +60,11 @@ def test_stencil_parity_with_oracle(gpu, orc, stencil, prec, n, boundary):
         s.variant = v
         s.set_field(sp.psi0)
         s.step(20, dt)
-        e = rel(s.get_field(), ref)
+        got = s.get_field()
+        e = rel(got, ref)
         say(f"[result] {stencil} {prec} n={n} variant {v}: rel L2 {e:.3e}")
         assert e <= TOL[prec]
+        assert line_err(got, ref) <= TOL[prec]
 
 
 @pytest.mark.parametrize("stencil", ["noncompact", "cd"])
@@ -122,10 +121,12 @@ def test_stencil3d_parity_with_oracle(gpu, orc, stencil, prec, n):
     s.set_field(psi.astype(s.dtype))
     say(f"[case] 3D {stencil} {prec} n={n}, 10 steps")
     s.step(10, dt)
-    e = rel(s.get_field(), ref)
+    got = s.get_field()
+    e = rel(got, ref)
     s.close()
     say(f"[result] 3D {stencil} {prec} n={n}: rel L2 {e:.3e}")
     assert e <= TOL[prec]
+    assert line_err(got, ref) <= TOL[prec]
 
 
 @pytest.mark.parametrize("stencil", ["noncompact", "cd"])
@@ -199,6 +200,7 @@ def test_stencil1d_parity_with_oracle(gpu, orc, stencil, prec, n):
     e = rel(outs[0], ref)
     say(f"[result] 1D {stencil} {prec} n={n}: rel L2 {e:.3e}")
     assert e <= TOL[prec]
+    assert line_err(outs[0], ref) <= TOL[prec]
 
 
 @pytest.mark.parametrize("dim,n", [(1, 300), (2, 90), (3, (37, 21, 30))])

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import nlse_inputs as I
+from parity_util import line_err, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -32,10 +33,6 @@ def gpu():
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def rel(a, b):
-    return float(np.linalg.norm((np.asarray(a, np.complex128) - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
 def whole_step_variants(s):
@@ -102,9 +99,11 @@ def test_whole_step_parity_with_oracle(gpu, orc, prec, n):
         s.set_field(sp.psi0)
         s.variant = v
         s.step(30, dt)
-        e = rel(s.get_field(), ref)
+        got = s.get_field()
+        e = rel(got, ref)
         say(f"[result] rel L2 {e:.3e}")
         assert e <= TOL[prec], (v, e)
+        assert line_err(got, ref) <= TOL[prec]
 
 
 def test_whole_step_no_potential_and_fixed_boundary(gpu, orc):
@@ -120,6 +119,7 @@ def test_whole_step_no_potential_and_fixed_boundary(gpu, orc):
         s.step(11, dt)
         g = s.get_field()
         assert rel(g, ref) <= 1e-12
+        assert line_err(g, ref) <= 1e-12
         m = np.zeros(psi.shape, bool)
         m[0, :] = m[-1, :] = m[:, 0] = m[:, -1] = True
         assert np.array_equal(g[m], psi[m]), "Dirichlet values must stay fixed"
@@ -172,7 +172,9 @@ def test_whole_step_full_size(gpu, orc):
             s.set_field(sp.psi0)
             s.variant = v
             s.step(2, dt)
-            e = rel(s.get_field(), ref)
+            got = s.get_field()
+            e = rel(got, ref)
             say(f"[result] rel L2 {e:.3e}")
             assert e <= TOL[prec], (prec, v, e)
+            assert line_err(got, ref) <= TOL[prec]
         s.close()
