@@ -98,8 +98,8 @@ def main(kind, variant2d, stage_variant, fetch_csv, write_csv, calib_json=None):
                 f"--no-msd --no-stage3d --steps3d 3 --variant3d {variant2d}")
         d = "prof3d"
     else:
-        args = (f"--steps 5 --warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned "
-                f"--variant2d {variant2d} --stage-variant {stage_variant}")
+        args = (f"--steps 5 --warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned --no-stencils "
+                f"--no-msd --variant2d {variant2d} --stage-variant {stage_variant}")
         d = "prof"
     out = {"kernel": NAMES[kind], "workload": WORKLOADS[kind][1],
            "source_sha": source_sha(kind), "sources": SOURCES[kind],
@@ -138,7 +138,7 @@ def valu(variant2d, csv_path, simds=1024, xcds=8):
            "command": "cd /tmp && rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_VALU_FLOPS_FP64 "
                       "SQ_INSTS_VALU_FLOPS_FP32 SQ_ACTIVE_INST_VALU SQ_BUSY_CU_CYCLES SQ_WAVES GRBM_GUI_ACTIVE "
                       "-d $R/gpurun_out/prof_valu -o pmc --output-format csv -- python3 $R/bench.py --steps 5 "
-                      "--warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned "
+                      "--warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned --no-stencils --no-msd "
                       f"--variant2d {variant2d}"}
     json.dump(out, open(valu_file(), "w"), indent=1)
     print(json.dumps(out, indent=1))
