@@ -144,6 +144,15 @@ def rollout_pairs(seed, params, scale, V, windows, noise=1e-3):
     s.close()
     m.close()
     del snaps
+    # windows where the corrected run has left the fine trajectory (non-finite, or farther from
+    # it than half its norm) are no training input: their targets are off the states it visits
+    # while it still tracks the fine run
+    d = torch.linalg.vector_norm((pred - ref).reshape(len(keep), -1), dim=1)
+    r = torch.linalg.vector_norm(ref.reshape(len(keep), -1), dim=1)
+    ok = torch.isfinite(d) & (d <= 0.5 * r)
+    if not bool(ok.all()):
+        idx = torch.nonzero(ok).flatten()
+        pred, ref = pred.index_select(0, idx), ref.index_select(0, idx)
     return (pred, ref), el
 
 
@@ -345,19 +354,36 @@ def main():
         losses = [float("nan")]
     t_train = time.perf_counter() - t0
     del pairs
-    # on-policy rounds: the corrected run's own states as inputs, the fine run as the target
+    # on-policy rounds: the corrected run's own states as inputs, the fine run as the target; a
+    # round's weights are kept only if they lower the validation error
+    rounds = []
+    if args.rollout_rounds:
+        best = float(np.mean([r["E_learned"] for r in evaluate(params, scale, val_seeds)]))
+        log(f"[rollout] validation E_learned before: {best:.4e}")
     for rnd in range(args.rollout_rounds):
         rp = []
         for sd in train_seeds:
             pr, el = rollout_pairs(sd, params, scale, Vc, args.windows, noise=args.train_noise)
-            rp.append(pr)
+            if pr[0].shape[0]:
+                rp.append(pr)
             t_data += el
-        log(f"[rollout] round {rnd}: {sum(p[0].shape[0] for p in rp)} on-policy pairs")
+            log(f"[rollout] round {rnd} seed {sd}: fine run {el:.2f}s, {pr[0].shape[0]} pairs")
+        npairs = sum(p[0].shape[0] for p in rp)
+        log(f"[rollout] round {rnd}: {npairs} on-policy pairs")
+        if not rp:
+            break
         t0 = time.perf_counter()
-        params, _, losses = train(rp, Vc, steps=args.rollout_steps, lr=args.lr * 0.25, batch=args.batch,
-                                  smooth=args.smooth, augment=args.augment, scale=scale, init=params, seed=rnd + 1)
+        cand, _, rl = train(rp, Vc, steps=args.rollout_steps, lr=args.lr * 0.25, batch=args.batch,
+                            smooth=args.smooth, augment=args.augment, scale=scale, init=params, seed=rnd + 1)
         t_train += time.perf_counter() - t0
         del rp
+        e = float(np.mean([r["E_learned"] for r in evaluate(cand, scale, val_seeds)]))
+        rounds.append({"round": rnd, "pairs": npairs, "loss_first": rl[0], "loss_last100": float(np.mean(rl[-100:])),
+                       "val_E_learned": e, "kept": bool(np.isfinite(e) and e < best)})
+        log(f"[rollout] round {rnd}: validation E_learned {e:.4e} (best {best:.4e})")
+        if not (np.isfinite(e) and e < best):
+            break
+        params, losses, best = cand, rl, e
     # the correction scale is chosen on validation seeds, never on the test seeds
     damp = tuple(float(v) for v in args.damping.split(","))
     val = evaluate(params, scale, val_seeds, damping=damp)
@@ -374,7 +400,8 @@ def main():
                  "train_steps": args.steps, "smooth": args.smooth, "damping": alpha, "val_E_by_damping": mean_val,
                  "t_data_s": t_data, "t_train_s": t_train, "loss_first": losses[0],
                  "loss_last100": float(np.mean(losses[-100:])), "scale": scale * alpha,
-                 "train_noise": args.train_noise, "rollout_rounds": args.rollout_rounds, "init": args.init})
+                 "train_noise": args.train_noise, "rollout_rounds": args.rollout_rounds, "init": args.init,
+                 "rollout": rounds})
     log(json.dumps(summ, indent=1, default=float))
     if args.report:
         json.dump({"summary": summ, "per_seed": res, "validation": val}, open(args.report, "w"), indent=1,
