@@ -160,7 +160,7 @@ int nlse_launches_per_step(const nlse_ctx *c);
  * least 2 intervals per axis) the whole-step kernels form the face values and the boundary
  * nodes of Eqs. msdbc_lap and msdbc_ut themselves, and the strips that hold a face column
  * take segments of about half as many rows; their results equal the MSD stage kernels' to the
- * last place except for rare one-unit differences of it that start on the face y = 0. */
+ * last place except for rare one-unit differences of it that start on the face y = 0.
  * 3D: 0-3 stage kernels with 64 x 4 or 64 x 8 column tiles marching 16, 32 or 64 planes;
  * 4-6 (Dirichlet, fields below 2^31 elements) two launches per step, each fusing two stages
  * (1+2, 3+4) on 64 x 16 or 64 x 8 column tiles marching 32 or 64 planes.
