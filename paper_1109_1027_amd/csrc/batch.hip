@@ -47,10 +47,10 @@ template <typename R, typename M> struct Batch1D { static constexpr int BS = 512
 template <> struct Batch1D<float, float> { static constexpr int BS = 1024, NPT = 9; };
 template <> struct Batch1D<float, double> { static constexpr int BS = 512, NPT = 17; };
 
-// 2D workgroups: 16 waves where the whole-step body fits 128 VGPRs (FP32: four waves per
-// SIMD), 8 waves otherwise.
+// 2D workgroups: 12 waves in FP32, whose whole-step body needs about 170 VGPRs (three waves per
+// SIMD; at 16 waves and 128 VGPRs it spills in the row loop), 8 waves otherwise.
 template <typename R, typename M> struct Batch2DWaves { static constexpr int v = 8; };
-template <> struct Batch2DWaves<float, float> { static constexpr int v = 16; };
+template <> struct Batch2DWaves<float, float> { static constexpr int v = 12; };
 
 __global__ void batch_reset_kernel(int *queue)
 {
@@ -62,7 +62,7 @@ template <typename R, typename M, int Q, int NW>
 __global__ __launch_bounds__(64 * NW) void batch2d_kernel(const BatchItem *items, const int *order, int n2d,
                                                           int *queue, int64_t nsteps)
 {
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];   // after s_item: keep 16-byte alignment
     __shared__ int s_item;
     auto *stg = reinterpret_cast<wave2d::Staging<R, Q> *>(smem);   // [NW], one per wave
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -113,7 +113,7 @@ template <typename R, typename M, int BS, int NPT>
 __global__ __launch_bounds__(BS) void batch1d_kernel(const BatchItem *items, const int *order, int n1d,
                                                            int *queue, int64_t nsteps)
 {
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];   // after s_item: keep 16-byte alignment
     __shared__ int s_item;
     for (;;) {
         __syncthreads();

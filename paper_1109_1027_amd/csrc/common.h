@@ -19,6 +19,36 @@ template <> struct cplx_t<double> { using type = double2; };
 template <> struct cplx_t<float> { using type = float2; };
 template <typename R> using C = typename cplx_t<R>::type;
 
+// Loads and stores of device memory through the global address space.  A pointer that a
+// kernel reads from memory (the batched launch takes its instances' fields from a table) is
+// generic to the compiler, and generic (flat) accesses are counted together with LDS accesses:
+// each wait for an LDS read would then also wait for every row load in flight.  These keep
+// such accesses global whatever the compiler knows of the pointer.
+typedef float dev_f2 __attribute__((ext_vector_type(2)));
+typedef double dev_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float dev_ld(const float *p) { return *(const __attribute__((address_space(1))) float *)p; }
+__device__ __forceinline__ double dev_ld(const double *p) { return *(const __attribute__((address_space(1))) double *)p; }
+__device__ __forceinline__ float2 dev_ld(const float2 *p)
+{
+    const dev_f2 v = *(const __attribute__((address_space(1))) dev_f2 *)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 dev_ld(const double2 *p)
+{
+    const dev_d2 v = *(const __attribute__((address_space(1))) dev_d2 *)p;
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void dev_st(float2 *p, float2 v)
+{
+    const dev_f2 w = {v.x, v.y};
+    *(__attribute__((address_space(1))) dev_f2 *)p = w;
+}
+__device__ __forceinline__ void dev_st(double2 *p, double2 v)
+{
+    const dev_d2 w = {v.x, v.y};
+    *(__attribute__((address_space(1))) dev_d2 *)p = w;
+}
+
 template <typename R>
 __host__ __device__ __forceinline__ C<R> mk(R x, R y) { C<R> r; r.x = x; r.y = y; return r; }
 

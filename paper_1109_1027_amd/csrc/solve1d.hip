@@ -15,7 +15,7 @@ template <> struct NPT1D<float> { static constexpr int v = 18; };
 template <typename R, typename M, int BS, int NPT, int ST>
 __global__ __launch_bounds__(BS) void solve1d_kernel(Solve1DArgs A)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     solve1d_onchip<R, M, BS, NPT, ST>(A, smem_raw);
 }
 

@@ -137,15 +137,15 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
     const C<R> *__restrict__ DBy = (const C<R> *)A.DB[1];
 
     // MSD reuses sdy: [0] F_b of row ny until its output row, [1] row 0 of a stage's input
-    if (!MSD) sdy[0][lane] = xin ? unscaled<R>(DBy[x], lc.h2) : czero<R>();   // unscaled, like d2u
-    if (!MSD) sdy[1][lane] = xin ? unscaled<R>(DBy[nx + 1 + x], lc.h2) : czero<R>();
+    if (!MSD) sdy[0][lane] = xin ? unscaled<R>(dev_ld(DBy + x), lc.h2) : czero<R>();   // unscaled, like d2u
+    if (!MSD) sdy[1][lane] = xin ? unscaled<R>(dev_ld(DBy + nx + 1 + x), lc.h2) : czero<R>();
     const R ih2 = (R)A.c.ih2, ia = (R)A.c.ia;
     if (!MSD && has_face) {
         for (int i = lane; i < FR; i += 64) {
             const int r = jb - HALO + i;
             const bool ok = r >= 0 && r <= ny;
-            sdx[0][i] = ok ? unscaled<R>(DBx[r], lc.h2) : czero<R>();
-            sdx[1][i] = ok ? unscaled<R>(DBx[ny + 1 + r], lc.h2) : czero<R>();
+            sdx[0][i] = ok ? unscaled<R>(dev_ld(DBx + r), lc.h2) : czero<R>();
+            sdx[1][i] = ok ? unscaled<R>(dev_ld(DBx + ny + 1 + r), lc.h2) : czero<R>();
         }
     }
     if (lane < 2 * RP) {
@@ -184,8 +184,8 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
     const int xc = min(max(x, 0), nx);
     auto load_row = [&](int y, C<M> &pv, R &vv) {
         const int o = min(max(y, 0), ny) * px + xc + ox;
-        pv = pin[o];
-        vv = V[o];
+        pv = dev_ld(pin + o);
+        vv = dev_ld(V + o);
     };
     // PD rows of Psi^n and V in flight ahead of the row being consumed
     C<M> pf[PD];
@@ -367,7 +367,7 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                                 const int k0 = (kr + 8) % 9;   // ring slot of row 0 (r - 1)
                                 // (assignments, not a select of addresses, keep the rings in registers)
                                 C<M> p0;
-                                if (st == 3) p0 = pin[xc + ox];   // stage 4: row 0's ring slot is reused by now
+                                if (st == 3) p0 = dev_ld(pin + xc + ox);   // stage 4: row 0's ring slot is reused by now
                                 else p0 = P[k0];
                                 C<R> ub;
                                 if (st == 0) ub = cvt<R, M>(P[k0]);
@@ -378,7 +378,7 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                                 } else if (st < 3) {
                                     Kq[k0] = kacc<R>(Kq[k0], Fb);
                                 } else if (wlane && ys == 1) {
-                                    pout[x + ox] = axpy_m<R, M>(p0, ck[3], cadd<R>(Kq[k0], Fb));
+                                    dev_st(pout + x + ox, axpy_m<R, M>(p0, ck[3], cadd<R>(Kq[k0], Fb)));
                                 }
                                 if (st < 3) {   // into the next stage's rings, where row 0 is row m'-1
                                     const C<R> o0 = cvt<R, M>(axpy_m<R, M>(p0, ckl[st], Fb));
@@ -400,7 +400,7 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                         if (!MSD || rin) Kq[kr] = kacc<R>(Kq[kr], F);
                         outv = cvt<R, M>(axpy_m<R, M>(P[kr], plain ? ckl[st] : ckl[st] * rowf, F));
                     } else if (wlane && r >= ys && (plain || r < y1)) {
-                        pout[r * px + x + ox] = axpy_m<R, M>(P[kr], ck[3], cadd<R>(Kq[kr], F));
+                        dev_st(pout + r * px + x + ox, axpy_m<R, M>(P[kr], ck[3], cadd<R>(Kq[kr], F)));
                     }
                 }
                 in = outv;
