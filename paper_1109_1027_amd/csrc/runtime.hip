@@ -321,6 +321,30 @@ int nlse_autotune(nlse_ctx *c, int reps, int force, int *chosen)
     return NLSE_OK;
 }
 
+// Copy between a pitched device array (rows of `width` bytes, `dpitch` apart) and contiguous
+// host memory, synchronously.  A pitched copy straight to or from pageable host memory has
+// returned stale data when the HIP runtime was instrumented (a kernel tracer), so the host data
+// goes through a contiguous device buffer: one linear host copy, one pitched device-to-device copy.
+static hipError_t pitched_host_copy(void *dev, size_t dpitch, void *host, size_t width, int64_t rows, bool to_dev,
+                                   hipStream_t st)
+{
+    const size_t bytes = width * (size_t)rows;
+    void *tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, bytes);
+    if (e != hipSuccess) return e;
+    if (to_dev) {
+        e = hipMemcpyAsync(tmp, host, bytes, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpy2DAsync(dev, dpitch, tmp, width, width, rows, hipMemcpyDeviceToDevice, st);
+    } else {
+        e = hipMemcpy2DAsync(tmp, width, dev, dpitch, width, rows, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(host, tmp, bytes, hipMemcpyDeviceToHost, st);
+    }
+    const hipError_t es = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = es;
+    (void)hipFree(tmp);
+    return e;
+}
+
 int nlse_create(nlse_ctx **out, const nlse_params *p)
 {
     if (!out || !p) return fail(NLSE_E_INVAL, "nlse_create: NULL argument");
@@ -382,9 +406,9 @@ int nlse_create(nlse_ctx **out, const nlse_params *p)
                 if (c->rR == 8) ((double *)host.data())[i] = p->V[i];
                 else ((float *)host.data())[i] = (float)p->V[i];
             }
-            hipError_t e = hipMemcpy2D((char *)c->V + c->L.ox * c->rR, c->L.px * c->rR, host.data(),
-                                       w * c->rR, w * c->rR, rows, hipMemcpyHostToDevice);
-            if (e != hipSuccess) rc = hipfail(e, "hipMemcpy2D(V)");
+            hipError_t e = pitched_host_copy((char *)c->V + c->L.ox * c->rR, c->L.px * c->rR, host.data(),
+                                             w * c->rR, rows, true, c->stream);
+            if (e != hipSuccess) rc = hipfail(e, "copy of V");
         }
     }
     if (!rc && p->ndim == 2 && !p->V) rc = alloc(&c->V0, T * c->rR);   // alloc zero-fills
@@ -424,14 +448,13 @@ static int copy_field(nlse_ctx *c, void *dev_field, void *user, int on_device, b
     const size_t es = c->esM;
     const int64_t rows = L.py * (L.nz + 1), w = L.nx + 1;
     char *dev = (char *)dev_field + L.ox * es;
-    if (to_dev) {
-        HIPTRY(hipMemcpy2DAsync(dev, L.px * es, user, w * es, w * es, rows,
-                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    if (!on_device) {
+        HIPTRY(pitched_host_copy(dev, L.px * es, user, w * es, rows, to_dev, c->stream));
+    } else if (to_dev) {
+        HIPTRY(hipMemcpy2DAsync(dev, L.px * es, user, w * es, w * es, rows, hipMemcpyDeviceToDevice, c->stream));
     } else {
-        HIPTRY(hipMemcpy2DAsync(user, w * es, dev, L.px * es, w * es, rows,
-                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+        HIPTRY(hipMemcpy2DAsync(user, w * es, dev, L.px * es, w * es, rows, hipMemcpyDeviceToDevice, c->stream));
     }
-    if (!on_device) HIPTRY(hipStreamSynchronize(c->stream));
     return NLSE_OK;
 }
 

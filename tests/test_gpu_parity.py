@@ -301,6 +301,23 @@ def test_device_pointer_roundtrip(gpu):
     assert np.array_equal(out.cpu().numpy(), sp.psi0.astype(np.complex64))
 
 
+def test_host_copy_roundtrips_back_to_back(gpu):
+    """Host arrays in and out of the padded layout, for differently shaped fields one after the
+    other (each round trip must return its own field, never a previous one), in every dimension
+    and both master types."""
+    rng = np.random.default_rng(11)
+    for dim, n in ((1, 64), (2, 64), (2, 300), (3, 40), (2, 65), (3, 9)):
+        for prec in ("f64", "f32"):
+            shape = (n + 1,) * dim
+            psi = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+            s = gpu.Solver(dim, n, 0.1, 0.5, -1.0, None, "dirichlet", prec)
+            psi = psi.astype(s.dtype)
+            say(f"[case] host round trip dim {dim} n {n} {prec}")
+            s.set_field(psi)
+            assert np.array_equal(s.get_field(), psi)
+            s.close()
+
+
 # ------------------------------------------------------- config 3 runs --
 
 @pytest.fixture(scope="module")
