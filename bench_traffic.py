@@ -105,7 +105,7 @@ def main(kind, variant2d, stage_variant, fetch_csv, write_csv, calib_json=None):
            "source_sha": source_sha(kind), "sources": SOURCES[kind],
            "per_launch_bytes": res, "raw_counter_bytes": raw,
            "scale_factors": {"FETCH_SIZE": fF, "WRITE_SIZE": fW, "calibration": calib},
-           "commands": [f"cd /tmp && rocprofv3 --pmc {c} -d $R/gpurun_out/{d}_{c} -o pmc --output-format csv "
+           "commands": [f"cd /tmp && rocprofv3 --pmc {c} -d /tmp/{d}_{c} -o pmc --output-format csv "
                         f"-- python3 $R/bench.py {args}" for c in ("FETCH_SIZE", "WRITE_SIZE")]}
     json.dump(out, open(traffic_file(kind), "w"), indent=1)
     print(json.dumps(out, indent=1))
@@ -137,7 +137,7 @@ def valu(variant2d, csv_path, simds=1024, xcds=8):
     out = {"kernel": NAMES["step2d"], "source_sha": source_sha("step2d"), "per_launch": res,
            "command": "cd /tmp && rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_VALU_FLOPS_FP64 "
                       "SQ_INSTS_VALU_FLOPS_FP32 SQ_ACTIVE_INST_VALU SQ_BUSY_CU_CYCLES SQ_WAVES GRBM_GUI_ACTIVE "
-                      "-d $R/gpurun_out/prof_valu -o pmc --output-format csv -- python3 $R/bench.py --steps 5 "
+                      "-d /tmp/prof_valu -o pmc --output-format csv -- python3 $R/bench.py --steps 5 "
                       "--warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned --no-stencils --no-msd "
                       f"--variant2d {variant2d}"}
     json.dump(out, open(valu_file(), "w"), indent=1)
