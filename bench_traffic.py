@@ -3,6 +3,7 @@
 Usage: python bench_traffic.py <step2d|stage2d> <variant2d> <stage_variant> <fetch_collection.csv> <write_collection.csv>
        python bench_traffic.py pair3d <variant3d> - <fetch_collection.csv> <write_collection.csv> [<calibration.json>]
        python bench_traffic.py valu <variant2d> <valu_counter_collection.csv>   (VALU issue of the whole-step kernel)
+       python bench_traffic.py valu_stencils <valu_counter_collection.csv>   (the same per Laplacian and instance)
 
 <variant2d>, <stage_variant> and <variant3d> are the per-precision kernel variants the counter runs
 of bench.py were given (--variant2d, --stage-variant, --variant3d), e.g. f64:6,f32:3,mixed:3.
@@ -144,8 +145,40 @@ def valu(variant2d, csv_path, simds=1024, xcds=8):
     print(json.dumps(out, indent=1))
 
 
+def valu_stencils(csv_path, simds=1024, xcds=8):
+    """VALU counters of the whole-step kernel for each Laplacian (template argument ST: 0 2SHOC,
+    1 non-compact, 2 CD) and each kernel instance of a counter run of bench.py with its stencil
+    section on; the same counters and issue formula as valu()."""
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(csv_path)):
+        if "step2d_kernel<" in r["Kernel_Name"]:
+            agg[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lap = {"0": "2shoc", "1": "noncompact", "2": "cd"}
+    res = {}
+    for name, cs in sorted(agg.items()):
+        m = re.search(r"step2d_kernel<(\w+), (\w+), (\d+), (\d+), (\d+), false>", name)
+        if not m:
+            continue
+        c = {n: sum(v) / len(v) for n, v in cs.items()}
+        cycles = c["GRBM_GUI_ACTIVE"] / xcds
+        key = f"<{m.group(1)}, {m.group(2)}, Q={m.group(3)}, rows in flight {m.group(4)}> {lap[m.group(5)]}"
+        res[key] = {"dispatches": len(cs["SQ_WAVES"]), "valu_issue": c["SQ_INSTS_VALU"] * 4 / (simds * cycles),
+                    "insts_valu": c["SQ_INSTS_VALU"], "insts_salu": c["SQ_INSTS_SALU"], "waves": c["SQ_WAVES"],
+                    "cycles_per_xcd": cycles}
+    out = {"kernel": "nlse::step2d_kernel, 2SHOC / non-compact / CD Laplacians", "source_sha": source_sha("step2d"),
+           "per_launch": res,
+           "command": "cd /tmp && rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_VALU_FLOPS_FP64 "
+                      "SQ_INSTS_VALU_FLOPS_FP32 SQ_ACTIVE_INST_VALU SQ_BUSY_CU_CYCLES SQ_WAVES GRBM_GUI_ACTIVE "
+                      "-d /tmp/prof_valu_st -o pmc --output-format csv -- python3 $R/bench.py --steps 5 "
+                      "--warmup 1 --no-cpu-baseline --n3d 0 --batch-steps 0 --no-learned --no-msd --precs f64,f32"}
+    json.dump(out, open(os.path.join(ROOT, "profiles", "valu_step2d_stencils_gp2d_2048.json"), "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "valu":
         valu(sys.argv[2], sys.argv[3])
+    elif sys.argv[1] == "valu_stencils":
+        valu_stencils(sys.argv[2])
     else:
         main(*sys.argv[1:7])
