@@ -36,5 +36,5 @@ struct nlse_ctx {
     double kmax = 0.0;
     bool have_field = false;
     int variant = 0;            // kernel variant (tile shape; in 2D also stage vs whole-step kernels)
-    int stencil = 0;            // 2D Laplacian: NLSE_STENCIL_* (the whole-step kernels are 2SHOC only)
+    int stencil = 0;            // 2D Laplacian: NLSE_STENCIL_*
 };

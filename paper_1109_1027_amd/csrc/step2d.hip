@@ -12,11 +12,12 @@
 // so the four stages run as a pipeline skewed by two rows: when row j of Psi^n
 // arrives, stage 1 produces row j-2 of its output, stage 2 row j-4, stage 3
 // row j-6 and stage 4 row j-8 of Psi^{n+1}.  Along y each stage keeps its last
-// three input rows and three D^y rows in registers; along x the neighbours come
-// from the adjacent lanes through DPP wave shifts (no LDS exchange, no barriers).  The
-// valid columns shrink by two per side and stage, so the middle 48 of the 64
-// lanes produce Psi^{n+1}: neighbouring strips overlap by 16 columns and
-// neighbouring segments by 16 rows of recomputed halo.
+// three input rows and three D^y rows in registers; along x each stage input row
+// also goes through a wave-private LDS ring, read two rows after it was written,
+// and the neighbours of D^x come from the adjacent lanes through DPP wave shifts
+// (no barriers).  The valid columns shrink by two per side and stage, so the
+// middle 48 of the 64 lanes produce Psi^{n+1}: neighbouring strips overlap by 16
+// columns and neighbouring segments by 16 rows of recomputed halo.
 //
 // Register rings.  Psi^n, V and K_tot are needed 2, 4, 6 and 8 rows after they
 // arrive, so they sit in 9-row rings; the per-stage row queues have length 3.
