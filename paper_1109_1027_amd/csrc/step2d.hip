@@ -61,7 +61,10 @@ __device__ __forceinline__ void step2d_body(const Step2DArgs &A, int strips, int
         seg = k / (strips - 2);
         const int xs = 1 + wave2d::SW * strip - wave2d::HALO;
         if (xs > 0 && xs + 63 < (int)A.L.nx) {   // no face column among the wave's lanes
-            wave2d::step2d_wave<R, M, Q, PD, ST, MSD, false>(A, strip, seg, threadIdx.x & 63, stg[wv]);
+            if (wave2d::meets_face_rows((int)A.L.ny, seg, Q))
+                wave2d::step2d_wave<R, M, Q, PD, ST, MSD, false>(A, strip, seg, threadIdx.x & 63, stg[wv]);
+            else   // nor a face row: the closure code of rows 0 and ny compiled out too
+                wave2d::step2d_wave<R, M, Q, PD, ST, MSD, false, false>(A, strip, seg, threadIdx.x & 63, stg[wv]);
             return;
         }
     } else {

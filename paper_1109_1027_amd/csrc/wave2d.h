@@ -29,6 +29,18 @@ __host__ __device__ inline int segments_ng(int64_t ny, int ng)
     return (int)((ny - 1 + sr - 1) / sr);
 }
 
+// Under MSD: whether the window of segment `seg` (ng row groups) meets a face row, i.e. starts
+// above row 0 or reaches input row ny + 1, where the closures of rows 0 and ny act (the window
+// placement is that of step2d_wave).
+__host__ __device__ inline bool meets_face_rows(int ny, int seg, int ng)
+{
+    const int sr = 9 * ng - 2 * HALO, yend = ny + 1;
+    const int ys = 1 + sr * seg;
+    const int y0 = seg == segments_ng(yend, ng) - 1 ? (yend - sr > 1 ? yend - sr : 1) : ys;
+    const int jb = y0 - HALO;
+    return jb < 0 || jb + 9 * ng >= ny;
+}
+
 constexpr int RP = 2;               // zero entries on each side of a ring row
 constexpr int RS = 64 + 2 * RP;     // ring row stride
 
@@ -88,7 +100,10 @@ __device__ __forceinline__ C<R> msd_face(C<R> ub, C<R> uq, R vb, R vq, C<R> dqx,
 // second-order CD.
 // EDGE = false: the caller guarantees that the wave's 64 columns hold no face column (x = 0, nx),
 // and the face code is compiled out (under MSD it is long, and the instruction cache is shared).
-template <typename R, typename M, int Q, int PD = 1, int ST = 0, bool MSD = false, bool EDGE = true>
+// YF = false (MSD): the caller guarantees that the task's window meets neither face row
+// (meets_face_rows), and the closures of rows 0 and ny are compiled out as well: they are long, and
+// every checked row group would carry them although only the first and last segments use them.
+template <typename R, typename M, int Q, int PD = 1, int ST = 0, bool MSD = false, bool EDGE = true, bool YF = true>
 __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int seg, int lane, Staging<R, Q> &S,
                                             int ng = Q)
 {
@@ -199,8 +214,9 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
     // r lies in 1 .. ny-1 and below y1, and the face columns take their values by a select.
     // That holds for g >= 2 when the newest row of stage 1 stays below the face,
     // jb + 9 g + 8 <= ny.
-    auto group = [&](const int g, auto plain_t) __attribute__((always_inline)) {   // inlined: the rings stay in registers
+    auto group = [&](const int g, auto plain_t, auto yf_t) __attribute__((always_inline)) {   // inlined: the rings stay in registers
         constexpr bool plain = decltype(plain_t)::value;
+        constexpr bool yf = decltype(yf_t)::value;
 #pragma unroll
         for (int p = 0; p < 9; ++p) {
             const int t = 9 * g + p;
@@ -258,7 +274,7 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                         if constexpr (!MSD) {
                             if (m - 1 == 0) dy = sdy[0][lane];
                             if (m - 1 == ny) dy = sdy[1][lane];
-                        } else if (m - 1 == ny) {   // closure of face row ny: b = row ny, q = row ny-1
+                        } else if (yf && m - 1 == ny) {   // closure of face row ny: b = row ny, q = row ny-1
                             const int kq = (p + 18 - 2 * (st + 1)) % 9;   // ring slot of row m-2
                             const C<R> *rb = ring[st][q2] + RP + lane;     // row ny (m-1)
                             const C<R> dbt = d2u<R>(rb[-1], U[st][q2], rb[1]);
@@ -269,7 +285,7 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                     }
                     D[st][q0] = dy;
                     if constexpr (MSD) {
-                        if (!plain && jb < 0 && m == 2) {   // closure of face row 0 (b = row 0, q = row 1)
+                        if (yf && !plain && jb < 0 && m == 2) {   // closure of face row 0 (b = row 0, q = row 1)
                             const int kq = (p + 18 - 2 * (st + 1)) % 9;   // ring slot of row 0 (m-2)
                             const C<R> *rq = ring[st][q2] + RP + lane;     // row 1 (m-1)
                             const C<R> dqx = d2u<R>(rq[-1], U[st][q2], rq[1]);
@@ -356,7 +372,7 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
                                                  d4nc<R>(ym2, Uq[st][1], u, Uq[st][3], yp2, i12h2));
                         F = rhs<R>(lap, u, Vq[kr], aR, s);
                     }
-                    if constexpr (MSD) {
+                    if constexpr (MSD && yf) {
                         if (!plain) {
                             if (m == ny + 1) {   // F_b of row ny (b-1 = row ny-1, this row), kept in LDS
                                 sdy[0][lane] = msd_fb<R>(w_bm1(F), U[st][q2]);
@@ -415,12 +431,13 @@ __device__ __forceinline__ void step2d_wave(const Step2DArgs &A, int strip, int 
     static_assert(Q >= 2, "the first two groups are the warm-up");
     // groups 2 .. gp-1 are plain: the newest row of stage 1 stays below the face (MSD: one row more)
     const int gp = min(ng, max(2, (ny - jb - 8 - (MSD ? 1 : 0)) / 9 + 1));
+    constexpr auto yf = std::integral_constant<bool, YF>{};
 #pragma unroll 1
-    for (int g = 0; g < 2; ++g) group(g, std::false_type{});
+    for (int g = 0; g < 2; ++g) group(g, std::false_type{}, yf);
 #pragma unroll 1
-    for (int g = 2; g < gp; ++g) group(g, std::true_type{});
+    for (int g = 2; g < gp; ++g) group(g, std::true_type{}, yf);
 #pragma unroll 1
-    for (int g = gp; g < ng; ++g) group(g, std::false_type{});
+    for (int g = gp; g < ng; ++g) group(g, std::false_type{}, yf);
 }
 
 }  // namespace wave2d
