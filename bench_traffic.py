@@ -30,7 +30,8 @@ GIB = float(1 << 30)
 
 # source files each kernel is compiled from (its .hip and every header it includes)
 SOURCES = {"stage2d": ["stage2d.hip", "tile2d.h", "point.h", "common.h", "kernels.h"],
-           "step2d": ["step2d.hip", "wave2d.h", "dpp.h", "point.h", "common.h", "kernels.h"],
+           "step2d": ["step2d.hip", "step2d_impl.h", "step2d_f64.hip", "step2d_f32.hip", "step2d_mixed.hip", "wave2d.h",
+                      "dpp.h", "point.h", "common.h", "kernels.h"],
            "pair3d": ["step3d.hip", "point.h", "common.h", "kernels.h"]}
 KEYS = {"stage2d": {"f64": ["stage2d_kernel<double, double, double"], "f32": ["stage2d_kernel<float, float, float"],
                     "mixed": ["stage2d_kernel<double, float, double", "stage2d_kernel<float, float, double"]},

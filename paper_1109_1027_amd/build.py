@@ -25,15 +25,16 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-# Per-file flags.  The 2D whole-step kernels unroll their nine-row loop completely (every register
-# ring index a constant); the MSD instances' loop body exceeds LLVM's default size limit for a
-# requested full unroll, and a rolled loop would put the rings in scratch memory.
-EXTRA = {"step2d.hip": ["-mllvm", "-pragma-unroll-threshold=40000"]}
+# Per-file flags.  The 2D whole-step kernels (step2d*.hip) unroll their nine-row loop completely
+# (every register ring index a constant); the MSD instances' loop body exceeds LLVM's default size
+# limit for a requested full unroll, and a rolled loop would put the rings in scratch memory.
+def extra_flags(name):
+    return ["-mllvm", "-pragma-unroll-threshold=40000"] if name.startswith("step2d") else []
 
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *extra_flags(os.path.basename(src)), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -43,8 +44,11 @@ def _compile(src):
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
+    # the whole-step kernels' units take longest: start them first
+    order = sorted(srcs, key=lambda f: not os.path.basename(f).startswith("step2d_"))
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        list(ex.map(_compile, order))
+    objs = [os.path.join(BUILD, os.path.basename(f) + ".o") for f in srcs]
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

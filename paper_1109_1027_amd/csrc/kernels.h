@@ -52,6 +52,14 @@ struct Step2DArgs {
     int msd;             // 1: MSD boundary (2SHOC only; boundary nodes of psi_out written too, DB unused)
 };
 hipError_t launch_step2d(Prec prec, const Step2DArgs &a, hipStream_t st);
+// its parts, one translation unit each (step2d_<prec>.hip: Dirichlet, every Laplacian;
+// step2d_msd_<prec>.hip: MSD)
+hipError_t launch_step2d_f64(const Step2DArgs &a, hipStream_t st);
+hipError_t launch_step2d_f32(const Step2DArgs &a, hipStream_t st);
+hipError_t launch_step2d_mixed(const Step2DArgs &a, hipStream_t st);
+hipError_t launch_step2d_msd_f64(const Step2DArgs &a, hipStream_t st);
+hipError_t launch_step2d_msd_f32(const Step2DArgs &a, hipStream_t st);
+hipError_t launch_step2d_msd_mixed(const Step2DArgs &a, hipStream_t st);
 int step2d_variants();
 
 // 3D step as two launches of two fused stages each (see step3d.hip): pair 1 reads
