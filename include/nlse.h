@@ -106,6 +106,10 @@ typedef struct {
 int nlse_create(nlse_ctx **out, const nlse_params *p);
 
 /* Copy a full field (all (n+1)^ndim nodes, boundary included) into the context.
+ * psi: contiguous, x fastest, the context's master type (complex128 for F64 and
+ * F32_MIXED, complex64 for F32); on_device nonzero: a device pointer, copied on the
+ * context stream; zero: host memory, copied through a temporary device buffer of the
+ * field's size (allocated and freed within the call; the call waits for the stream).
  * Under Dirichlet the boundary values given here are held fixed from then on.
  * Also evaluates the stability bound of nlse_max_dt on this field (waits for
  * the stream) and stores it for nlse_step's check. */
@@ -117,7 +121,9 @@ int nlse_set_field(nlse_ctx *c, const void *psi, int on_device);
  * was created with allow_unstable = 0; NLSE_E_INVAL for dt <= 0 or nsteps < 0. */
 int nlse_step(nlse_ctx *c, int64_t nsteps, double dt);
 
-/* Copy the current field out (same layout and element type as nlse_set_field). */
+/* Copy the current field out (same layout and element type as nlse_set_field; host
+ * memory goes through a temporary device buffer as there, and the call waits for the
+ * stream; a device pointer is filled asynchronously on the context stream). */
 int nlse_get_field(nlse_ctx *c, void *out, int on_device);
 
 /* Mass h^d sum_{all nodes} |Psi|^2, accumulated in FP64 in a fixed order
