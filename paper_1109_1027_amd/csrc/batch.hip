@@ -8,7 +8,7 @@
 // their queue (longest first) and advance the popped instance through all
 // requested steps before popping again:
 //   - 2D kernel: an instance advances by whole RK4 steps (wave2d.h); the waves of
-//     the workgroup (16 in FP32, where the body fits 128 VGPRs, else 8) share out
+//     the workgroup (12 in FP32, three per SIMD at the body's ~170 VGPRs, else 8) share out
 //     its (strip, row segment) tasks, reading Psi^n and V and writing Psi^{n+1}
 //     into the instance's second master buffer, one workgroup barrier per step; an
 //     odd step count ends with a copy back;
